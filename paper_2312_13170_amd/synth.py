@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds none of the kernels' arithmetic: it only produces input
+arrays.  Random numbers come from SplitMix64 (Steele, Lea and Flood,
+"Fast splittable pseudorandom number generators", OOPSLA 2014) used as a
+counter-based generator: output i of a stream with key s is
+mix(s + (i + 1) * GAMMA), which is exactly the i-th output of the published
+sequential SplitMix64 started from state s.  numpy uint64 arithmetic wraps
+modulo 2**64, so the bytes do not depend on the numpy version.
+
+Conversions:
+  uniform24(x)  = (x >> 40) * 2**-24      in [0, 1), exact in float32
+  uniform53(x)  = (x >> 11) * 2**-53      in [0, 1), double
+  U[-1, 1)      = 2 * uniform24 - 1       exact in float32
+  N(0, 1)       = Box-Muller on two uniform53 draws, in double
+"""
+from __future__ import annotations
+
+import math
+import zlib
+from dataclasses import dataclass, field
+from typing import Dict, List
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64(key: int, n: int, offset: int = 0) -> np.ndarray:
+    """Outputs offset .. offset+n-1 of SplitMix64 started from state `key`."""
+    ctr = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        state = np.uint64(key & 0xFFFFFFFFFFFFFFFF) + ctr * GAMMA
+    return _mix(state)
+
+
+def stream_key(seed: int, name: str) -> int:
+    """64-bit key of the named sub-stream of a seed."""
+    tag = zlib.crc32(name.encode("utf-8"))
+    v = splitmix64(((seed & 0xFFFFFFFF) << 32) | tag, 1)[0]
+    return int(v)
+
+
+def uniform24(x: np.ndarray) -> np.ndarray:
+    return (x >> np.uint64(40)).astype(np.float64) * (2.0 ** -24)
+
+
+def uniform53(x: np.ndarray) -> np.ndarray:
+    return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def uniform_pm1(seed: int, name: str, shape) -> np.ndarray:
+    """float32 values in [-1, 1) on a 2**-23 grid."""
+    n = int(np.prod(shape)) if len(shape) else 1
+    u = uniform24(splitmix64(stream_key(seed, name), n))
+    return (2.0 * u - 1.0).astype(np.float32).reshape(shape)
+
+
+def uniform_range(seed: int, name: str, n: int, lo: float, hi: float) -> np.ndarray:
+    """float64 values in [lo, hi)."""
+    u = uniform53(splitmix64(stream_key(seed, name), n))
+    return lo + (hi - lo) * u
+
+
+def normal(seed: int, name: str, n: int) -> np.ndarray:
+    """Standard normal draws in double (Box-Muller, cosine branch)."""
+    x = splitmix64(stream_key(seed, name), 2 * n)
+    u1 = uniform53(x[0::2])
+    u2 = uniform53(x[1::2])
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def bernoulli(seed: int, name: str, shape, p: float) -> np.ndarray:
+    n = int(np.prod(shape))
+    return (uniform53(splitmix64(stream_key(seed, name), n)) < p).reshape(shape)
+
+
+def integer_matrix(seed: int, name: str, shape, lo: int, hi: int) -> np.ndarray:
+    """float32 matrix of integers uniform in [lo, hi]."""
+    n = int(np.prod(shape))
+    x = splitmix64(stream_key(seed, name), n)
+    span = np.uint64(hi - lo + 1)
+    return ((x % span).astype(np.int64) + lo).astype(np.float32).reshape(shape)
+
+
+# ---------------------------------------------------------------------------
+# Workloads.  Sizes and distributions of the five synthetic configurations;
+# seed of configuration i is i + 1 unless given.
+# ---------------------------------------------------------------------------
+
+def gemm_inputs(M, N, K, seed, alpha=1.5, beta=1.2):
+    return dict(kind="gemm", M=M, N=N, K=K, alpha=alpha, beta=beta,
+                A=uniform_pm1(seed, "A", (M, K)),
+                B=uniform_pm1(seed, "B", (K, N)),
+                C=uniform_pm1(seed, "C", (M, N)))
+
+
+def mm2_inputs(NI, NJ, NK, NL, seed, alpha=1.5, beta=1.2):
+    return dict(kind="mm2", NI=NI, NJ=NJ, NK=NK, NL=NL, alpha=alpha, beta=beta,
+                A=uniform_pm1(seed, "A", (NI, NK)),
+                B=uniform_pm1(seed, "B", (NK, NJ)),
+                C=uniform_pm1(seed, "C", (NJ, NL)),
+                D=uniform_pm1(seed, "D", (NI, NL)))
+
+
+def stats_inputs(N, M, seed, eps=0.1):
+    """data[i][j] = mu_j + sigma_j * z_ij, mu_j ~ U[-10,10), sigma_j ~ U[0.1,5)."""
+    mu = uniform_range(seed, "mu", M, -10.0, 10.0)
+    sigma = uniform_range(seed, "sigma", M, 0.1, 5.0)
+    z = normal(seed, "z", N * M).reshape(N, M)
+    data = (mu[None, :] + sigma[None, :] * z).astype(np.float32)
+    return dict(kind="stats", N=N, M=M, eps=eps, data=data, mu=mu, sigma=sigma)
+
+
+def precision_inputs(M, N, K, seed, outlier_p=0.01, outlier_scale=1e3):
+    A = uniform_pm1(seed, "A", (M, K))
+    B = uniform_pm1(seed, "B", (K, N))
+    A[bernoulli(seed, "A_out", (M, K), outlier_p)] *= np.float32(outlier_scale)
+    B[bernoulli(seed, "B_out", (K, N), outlier_p)] *= np.float32(outlier_scale)
+    return dict(kind="precision", M=M, N=N, K=K, alpha=1.0, beta=0.0, A=A, B=B)
+
+
+def loguniform_sizes(seed: int, name: str, n: int, lo: int = 32, hi: int = 1024) -> np.ndarray:
+    """v = exp(ln lo + U * (ln hi - ln lo)), rounded half-to-even, clamped."""
+    u = uniform53(splitmix64(stream_key(seed, name), n))
+    v = np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))
+    return np.clip(np.rint(v), lo, hi).astype(np.int64)
+
+
+@dataclass
+class Batch:
+    gemm: List[Dict] = field(default_factory=list)
+    cov: List[Dict] = field(default_factory=list)
+
+
+def batch_inputs(seed: int, n_gemm: int = 512, n_cov: int = 512, with_data: bool = True) -> Batch:
+    """Uneven instances: M, N, K log-uniform in [32, 1024] per instance."""
+    b = Batch()
+    gM = loguniform_sizes(seed, "gemm_M", n_gemm)
+    gN = loguniform_sizes(seed, "gemm_N", n_gemm)
+    gK = loguniform_sizes(seed, "gemm_K", n_gemm)
+    for t in range(n_gemm):
+        M, N, K = int(gM[t]), int(gN[t]), int(gK[t])
+        d = dict(kind="gemm", M=M, N=N, K=K, alpha=1.5, beta=1.2)
+        if with_data:
+            d["A"] = uniform_pm1(seed, "gA%d" % t, (M, K))
+            d["B"] = uniform_pm1(seed, "gB%d" % t, (K, N))
+            d["C"] = uniform_pm1(seed, "gC%d" % t, (M, N))
+        b.gemm.append(d)
+    cM = loguniform_sizes(seed, "cov_M", n_cov)
+    cN = loguniform_sizes(seed, "cov_N", n_cov)
+    for t in range(n_cov):
+        M, N = int(cM[t]), int(cN[t])
+        d = dict(kind="cov", M=M, N=N)
+        if with_data:
+            d["data"] = uniform_pm1(seed, "cX%d" % t, (N, M))
+        b.cov.append(d)
+    return b
+
+
+def config(i: int, seed: int | None = None, **kw):
+    """Inputs of synthetic configuration i (0..4)."""
+    s = i + 1 if seed is None else seed
+    if i == 0:
+        return gemm_inputs(256, 256, 256, s)
+    if i == 1:
+        return mm2_inputs(2048, 2048, 2048, 2048, s)
+    if i == 2:
+        return stats_inputs(4096, 2048, s)
+    if i == 3:
+        return precision_inputs(8192, 8192, 8192, s)
+    if i == 4:
+        return batch_inputs(s, **kw)
+    raise ValueError("configuration index must be 0..4")
+
