@@ -1,0 +1,288 @@
+#!/usr/bin/env python3
+"""Benchmark of the loop-internalised contraction kernels on one MI355X.
+
+Headline workload: the FP32 two-GEMM chain D = alpha*(A*B)*C + beta*D with
+NI = NJ = NK = NL = 2048 (tmp kept in HBM), inputs uniform in [-1, 1) from
+seed 2, alpha = 1.5, beta = 1.2.  One step is one li_mm2 call (two FP32
+matrix-core GEMM launches).  W untimed warm-up steps, then K timed steps
+between HIP events on the stream the kernels run on; inputs are resident in
+HBM before timing starts.
+
+Printed: one JSON line with the contract fields, plus
+  roofline      dominant kernel (the FP32 GEMM) vs the FP32 matrix peak,
+  cpu_baseline  the FP64 oracle timed on the host cores,
+  rows          the other kernels of the path, measured the same way
+                (mean of 30 timed runs after one warm-up).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense bf16/fp16 matrix
+PEAK_HBM = 8000.0        # GB/s
+
+
+def gemm_flops(M, N, K):
+    """Algorithmic flops of C = alpha*A*B + beta*C."""
+    return 2.0 * M * N * K + 3.0 * M * N
+
+
+def syrk_flops(M, N):
+    """Flops of the symmetric contraction of N samples x M features
+    (upper triangle including the diagonal, N multiply-adds each)."""
+    return float(N) * M * (M + 1)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=30)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--main-only", action="store_true", help="skip the other kernels' rows")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped",
+                   help="comma list of extra rows to measure")
+    return p.parse_args()
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every li_* call uses)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def time(self, fn, reps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s = torch.cuda.Event(enable_timing=True)
+        e = torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps  # ms per call
+
+    def time_each(self, fn, reps, warmup):
+        """per-call times (ms) for mean / median / min."""
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            fn()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
+def calib_copy(torch):
+    """A plain 256 MiB device copy: the reference kernel for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the kernels run on a single MI355X and this "
+              "build has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2312_13170_amd import li, synth
+
+    torch.cuda.set_device(0)
+    li.li_init()
+    timer = Timer(torch)
+    calib_copy(torch)
+
+    # ---------------------------------------------------------------- headline: 2mm 2048^4
+    c = synth.config(1)
+    NI, NJ, NK, NL = c["NI"], c["NJ"], c["NK"], c["NL"]
+    dA, dB, dC = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+    dD0 = torch.from_numpy(c["D"]).cuda()
+    dD = dD0.clone()
+    tmp = torch.empty((NI, NJ), device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        li.li_mm2(NI, NJ, NK, NL, c["alpha"], c["beta"], dA, dB, tmp, dC, dD)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    for _ in range(args.steps):
+        step()
+    t_end.record()
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    f1 = gemm_flops(NI, NJ, NK)
+    f2 = gemm_flops(NI, NL, NJ)
+    flops_step = f1 + f2
+    value = flops_step / (ms_step * 1e-3) / 1e9
+    # every kernel in the step is the FP32 GEMM (two launches of one shape)
+    launch_ms = ms_total / (2 * args.steps)
+    achieved = f1 / (launch_ms * 1e-3) / 1e12
+
+    # result of one clean step for the error check (D is updated in place)
+    dD.copy_(dD0)
+    step()
+    torch.cuda.synchronize()
+    D_gpu = dD.cpu().numpy()
+
+    out = {
+        "metric": "GFLOP/s and % of MFMA/HBM roofline per kernel; max rel err vs FP64 oracle",
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2mm FP32 NI=NJ=NK=NL=2048, alpha=1.5, beta=1.2, tmp in HBM, seed 2",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "kernel": "gemm_f32_kernel (2048x2048x2048)",
+                     "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": None},
+    }
+
+    if not args.main_only:
+        out["rows"] = measure_rows(args, torch, li, synth, timer)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["max_rel_err"] = cpu_baseline(c, D_gpu, flops_step)
+
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(c, D_gpu, flops_step):
+    """The FP64 oracle (plain loop nests) on the host cores: the whole 2mm
+    workload once; also gives the normwise error of the GPU result."""
+    import oracle
+
+    oracle._load()
+    t0 = time.perf_counter()
+    _, D = oracle.mm2(c["A"], c["B"], c["C"], c["D"], alpha=c["alpha"], beta=c["beta"])
+    dt = time.perf_counter() - t0
+    err = oracle.normwise_error(D_gpu, D)
+    base = {"value": round(flops_step / dt / 1e9, 2), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "full 2mm 2048^4 workload, one run, %.2f s" % dt}
+    return base, {"2mm_D": err}
+
+
+def measure_rows(args, torch, li, synth, timer):
+    rows = {}
+    want = set(r for r in args.rows.split(",") if r)
+    reps = 30
+
+    if "gemm256" in want:
+        c = synth.config(0)
+        A, B, C0 = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+        C = C0.clone()
+        ms = timer.time(lambda: li.li_gemm(256, 256, 256, 1.5, A, B, 1.2, C), reps, 1)
+        f = gemm_flops(256, 256, 256)
+        rows["gemm_256"] = {"ms": round(ms, 5), "GFLOP/s": round(f / ms / 1e6, 1), "bound": "launch"}
+        del A, B, C0, C
+
+    if "cov" in want or "corr" in want:
+        s = synth.config(2)
+        X = torch.from_numpy(s["data"]).cuda()
+        N, M = s["N"], s["M"]
+        Y = torch.empty_like(X)
+        mean = torch.empty(M, dtype=torch.float64, device="cuda")
+        std = torch.empty(M, dtype=torch.float64, device="cuda")
+        out = torch.empty((M, M), device="cuda")
+        ws = torch.empty(li.li_stats_workspace_bytes(M, N) // 8 + 1, dtype=torch.float64, device="cuda")
+        f = syrk_flops(M, N)
+        for kind in ("cov", "corr"):
+            if kind not in want:
+                continue
+            if kind == "cov":
+                fn = lambda: li.li_covariance(M, N, X, Y, mean, out, ws)
+            else:
+                fn = lambda: li.li_correlation(M, N, 0.1, X, Y, mean, std, out, ws)
+            ms = timer.time(fn, reps, 1)
+            rows[kind + "_4096x2048"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
+                                         "frac_fp32_mfma": round(f / ms / 1e9 / PEAK_FP32_MFMA, 4)}
+        del X, Y, out, ws
+
+    if "precision" in want:
+        p = synth.config(3)
+        M = N = K = 8192
+        A, B = torch.from_numpy(p["A"]).cuda(), torch.from_numpy(p["B"]).cuda()
+        C = torch.empty((M, N), device="cuda")
+        ws = torch.empty(li.li_gemm_ex_workspace_bytes(M, N, K, "bf16x3") // 4 + 1, device="cuda")
+        f = gemm_flops(M, N, K)
+        for prec in ("fp32", "bf16", "fp16", "bf16x3"):
+            fn = lambda: li.li_gemm_ex(M, N, K, 1.0, A, B, 0.0, C, prec, ws)
+            ms = timer.time(fn, 10, 1)
+            peak = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
+            rows["gemm_8192_" + prec] = {"ms": round(ms, 3), "TFLOP/s": round(f / ms / 1e9, 1),
+                                         "frac_peak": round(f / ms / 1e9 / peak, 4)}
+        del A, B, C, ws
+
+    if "grouped" in want:
+        try:
+            rows["grouped"] = measure_grouped(torch, li, synth, timer)
+        except Exception as exc:  # grouped plans may be absent from a build
+            rows["grouped"] = {"error": str(exc)}
+    return rows
+
+
+def measure_grouped(torch, li, synth, timer):
+    b = synth.config(4)
+    keep = []
+    probs = []
+    for d in b.gemm:
+        A, B, C = (torch.from_numpy(d[k]).cuda() for k in ("A", "B", "C"))
+        keep += [A, B, C]
+        probs.append(li.make_problem(li.LI_PROBLEM_GEMM, d["M"], d["N"], d["K"], d["alpha"], d["beta"],
+                                     A, B, C))
+    for d in b.cov:
+        X = torch.from_numpy(d["data"]).cuda()
+        Y = torch.empty_like(X)
+        mean = torch.empty(d["M"], dtype=torch.float64, device="cuda")
+        cov = torch.empty((d["M"], d["M"]), device="cuda")
+        keep += [X, Y, mean, cov]
+        probs.append(li.make_problem(li.LI_PROBLEM_COVARIANCE, d["M"], d["N"], 0, 1.0, 0.0, X, None, cov,
+                                     Y, mean))
+    plan = li.li_group_plan_create(probs)
+    f = plan.flops
+    ms_g = timer.time(plan.launch, 30, 1)
+    ms_l = timer.time(plan.launch_loop, 5, 1)
+    plan.close()
+    return {"instances": len(probs), "GFLOP": round(f / 1e9, 3), "grouped_ms": round(ms_g, 4),
+            "grouped_GFLOP/s": round(f / ms_g / 1e6, 1), "loop_ms": round(ms_l, 4),
+            "loop_GFLOP/s": round(f / ms_l / 1e6, 1), "speedup": round(ms_l / ms_g, 2)}
+
+
+if __name__ == "__main__":
+    main()

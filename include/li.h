@@ -1,0 +1,206 @@
+/*
+ * li.h -- C ABI of libli.so: loop-internalised contraction kernels for
+ * AMD MI355X (gfx950).
+ *
+ * The operations are the loop nests that the paper's device optimisations
+ * target ("Experiences Building an MLIR-based SYCL Compiler", arXiv
+ * 2312.13170): the matrix-multiply work-item kernel of Sec. VI-C (loop
+ * internalization, which stages the reduction loop's operand tiles in local
+ * memory) and the polybench GEMM, 2mm, covariance and correlation kernels of
+ * Sec. VIII, whose reduction sites Sec. VI-B (detect reduction) keeps in
+ * registers.  Here they are hand-written HIP kernels: operand tiles go
+ * through double-buffered LDS, accumulation stays in matrix-core registers.
+ *
+ * Conventions (all entry points)
+ *  - Memory model: like SYCL unified shared memory (Sec. II-A), callers pass
+ *    raw device pointers they allocated and own; the library never frees or
+ *    copies caller memory.  Every matrix is dense and row-major.
+ *  - Ordering: every call enqueues work on `stream` (a hipStream_t; NULL is
+ *    the default stream) and returns without synchronising.  Work on one
+ *    stream runs in call order, the analogue of a SYCL queue.  A device fault
+ *    surfaces as a HIP error at the caller's next synchronisation.
+ *  - Validation runs on the host before any launch: negative sizes, a NULL
+ *    pointer for an operand that will be read or written, an output that
+ *    overlaps an input (except where stated), a too-small workspace or an
+ *    unknown enum value return an error and launch nothing.  The
+ *    no-overlap rule is the run-time form of the alias checks that the
+ *    paper's transformations rely on (Sec. V-A, VI-A).
+ *  - Degenerate sizes: a zero output extent is a no-op; K == 0 gives
+ *    C = beta*C; alpha == 0 means A and B are not read; beta == 0 means C
+ *    is not read (NaN in C does not propagate).
+ *  - Device: the current HIP device must be gfx950; otherwise
+ *    LI_ERR_UNSUPPORTED_DEVICE.  There is no fallback path.
+ *  - Errors: a non-zero li_status; li_last_error() gives a message for the
+ *    calling thread's last failure.
+ */
+#ifndef LI_H
+#define LI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t li_status;
+typedef void *li_stream; /* hipStream_t */
+
+enum {
+    LI_OK = 0,
+    LI_ERR_INVALID_SIZE = 1,
+    LI_ERR_NULL_POINTER = 2,
+    LI_ERR_OVERLAP = 3,
+    LI_ERR_WORKSPACE = 4,
+    LI_ERR_BAD_ENUM = 5,
+    LI_ERR_UNSUPPORTED_DEVICE = 6,
+    LI_ERR_HIP = 7,
+    LI_ERR_NOT_FOUND = 8
+};
+
+typedef enum {
+    LI_FP32 = 0,   /* FP32 operands, FP32 matrix-core products           */
+    LI_BF16 = 1,   /* operands rounded to bfloat16 (nearest-even)        */
+    LI_FP16 = 2,   /* operands rounded to binary16 (nearest-even)        */
+    LI_BF16X3 = 3  /* split bf16: X = Xh + Xl, Ah*Bh + Ah*Bl + Al*Bh     */
+} li_precision;
+
+/* Message describing the calling thread's last non-OK status ("" if none). */
+const char *li_last_error(void);
+
+/* Library version string. */
+const char *li_version(void);
+
+/* Check that the current device is gfx950 and cache its properties.
+ * Called implicitly by every entry point; may be called up front. */
+li_status li_init(void);
+
+/* GEMM (Sec. VI-C listing of the matrix multiply; polybench GEMM, Sec. VIII):
+ *   C = alpha * A * B + beta * C
+ * A: M x K, B: K x N, C: M x N, FP32 device pointers.  C must not overlap A
+ * or B.  FP32 matrix-core products with FP32 accumulation. */
+li_status li_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                  const float *B, float beta, float *C, li_stream stream);
+
+/* GEMM with a chosen operand precision.  FP32 inputs and output as in
+ * li_gemm; LI_BF16 / LI_FP16 round A and B to the 16-bit format and
+ * multiply on the matrix cores with FP32 accumulation; LI_BF16X3 splits each
+ * operand X into Xh = bf16(X), Xl = bf16(X - Xh) and accumulates
+ * Ah*Bh + Ah*Bl + Al*Bh.  The 16-bit copies of A and B live in `workspace`
+ * (caller-owned device memory of at least li_gemm_ex_workspace_bytes bytes;
+ * may be NULL for LI_FP32).  LI_FP16 turns magnitudes beyond 65504 into
+ * infinities, as the format does. */
+size_t li_gemm_ex_workspace_bytes(int64_t M, int64_t N, int64_t K, li_precision p);
+li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                     const float *B, float beta, float *C, li_precision p,
+                     void *workspace, size_t workspace_bytes, li_stream stream);
+
+/* 2mm (polybench two-GEMM chain, Sec. VIII):
+ *   tmp = alpha * A * B        A: NI x NK, B: NK x NJ, tmp: NI x NJ (written)
+ *   D   = tmp * C + beta * D   C: NJ x NL, D: NI x NL (read and written)
+ * tmp is a caller buffer in device memory and is a result.  tmp and D must
+ * not overlap any input or each other. */
+li_status li_mm2(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, float alpha, float beta,
+                 const float *A, const float *B, float *tmp, const float *C, float *D,
+                 li_stream stream);
+
+/* Covariance and correlation (polybench kernels, Sec. VIII; their column
+ * sums are the array-reduction sites of Sec. VI-B).
+ * data: N samples x M features (row-major), FP32.
+ * Column means (and, for correlation, population standard deviations) are
+ * accumulated in FP64 and returned as FP64 arrays of length M.
+ *   covariance:  data_out = data - mean (per column, FP64 then one FP32
+ *                rounding); cov = data_out^T data_out / (N - 1), M x M FP32,
+ *                full symmetric (lower triangle is the bitwise mirror).
+ *                Requires N >= 2.
+ *   correlation: stddev[j] <= eps is replaced by 1.0;
+ *                data_out = (data - mean) / (sqrt(N) * stddev);
+ *                corr = data_out^T data_out with the diagonal exactly 1.0.
+ *                Requires N >= 1.
+ * data_out may equal data (in place, as the loop nests do) but must not
+ * partially overlap it; mean, stddev and cov/corr must not overlap anything.
+ * `workspace` is caller-owned device memory of at least
+ * li_stats_workspace_bytes(M, N) bytes (FP64 partial sums). */
+size_t li_stats_workspace_bytes(int64_t M, int64_t N);
+li_status li_covariance(int64_t M, int64_t N, const float *data, float *data_out,
+                        double *mean, float *cov, void *workspace, size_t workspace_bytes,
+                        li_stream stream);
+li_status li_correlation(int64_t M, int64_t N, double eps, const float *data,
+                         float *data_out, double *mean, double *stddev, float *corr,
+                         void *workspace, size_t workspace_bytes, li_stream stream);
+
+/* Split pre-pass of the LI_BF16X3 precision: hi[i] = bf16(x[i]),
+ * lo[i] = bf16(x[i] - hi[i]), stored as raw bfloat16 bit patterns (uint16).
+ * Also the conversion check of the 16-bit formats: with lo == NULL only hi
+ * is written.  p selects LI_BF16 (lo allowed) or LI_FP16 (lo must be NULL). */
+li_status li_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, li_precision p,
+                     li_stream stream);
+
+/* ---------------------------------------------------------------------
+ * Grouped execution: many independent, uneven GEMM and covariance
+ * problems in one persistent launch sequence captured as a HIP graph.
+ * ------------------------------------------------------------------- */
+typedef enum { LI_PROBLEM_GEMM = 0, LI_PROBLEM_COVARIANCE = 1 } li_problem_kind;
+
+typedef struct li_problem {
+    int32_t kind;          /* li_problem_kind                                   */
+    int32_t reserved;
+    int64_t M, N, K;       /* GEMM: C(MxN) = alpha A(MxK) B(KxN) + beta C;
+                              covariance: M features, N samples, K unused      */
+    float alpha, beta;     /* GEMM only                                         */
+    const float *A;        /* GEMM: A; covariance: data (N x M)                 */
+    const float *B;        /* GEMM: B; covariance: unused (NULL)                */
+    float *C;              /* GEMM: C; covariance: cov (M x M)                  */
+    float *data_out;       /* covariance: centred data (N x M), may equal A     */
+    double *mean;          /* covariance: FP64 column means (M)                 */
+} li_problem;
+
+typedef struct li_group_plan li_group_plan;
+
+/* Build a plan for `count` problems: picks a tile shape per problem from
+ * the tuning table, uploads a descriptor table (the library allocates it)
+ * and instantiates a HIP graph of the grouped kernels.  Pointers inside
+ * the problems are captured; the caller keeps those buffers alive. */
+li_status li_group_plan_create(const li_problem *problems, int32_t count,
+                               li_group_plan **plan);
+/* Launch the plan's graph on `stream` (asynchronous). */
+li_status li_group_plan_launch(li_group_plan *plan, li_stream stream);
+/* Run the same work as individual kernel launches (no graph, no grouping):
+ * the per-instance launch loop, kept for comparison. */
+li_status li_group_plan_launch_loop(li_group_plan *plan, li_stream stream);
+/* Total algorithmic flops of the plan's problems. */
+double li_group_plan_flops(const li_group_plan *plan);
+void li_group_plan_destroy(li_group_plan *plan);
+
+/* ---------------------------------------------------------------------
+ * Tile-shape tuning.  Kernel families: LI_KERNEL_GEMM_F32 (also used by
+ * 2mm), LI_KERNEL_SYRK_F32 (the covariance/correlation contraction),
+ * LI_KERNEL_GEMM_LP (bf16/fp16/split products).  Each family has a fixed
+ * list of compiled tile shapes; the table maps a size bucket to one of
+ * them.  The search itself (timing candidates) runs outside the library.
+ * ------------------------------------------------------------------- */
+enum { LI_KERNEL_GEMM_F32 = 0, LI_KERNEL_SYRK_F32 = 1, LI_KERNEL_GEMM_LP = 2 };
+
+typedef struct li_tile_config {
+    int32_t bm, bn, bk;     /* block tile and K-tile                    */
+    int32_t waves_m, waves_n;
+    int32_t split_k;        /* reduction split (1 = none)               */
+} li_tile_config;
+
+int32_t li_tune_num_candidates(int32_t kernel);
+li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out);
+/* Size bucket of a problem: bucket = the number of bits of max(M, N, K)
+ * (0..63); problems in one bucket share a table entry. */
+int32_t li_tune_bucket(int64_t M, int64_t N, int64_t K);
+/* Set / get the candidate used for (kernel, bucket); -1 restores the
+ * built-in default. */
+li_status li_tune_set(int32_t kernel, int32_t bucket, int32_t index);
+int32_t li_tune_get(int32_t kernel, int32_t bucket);
+/* Force one candidate for every call of a family (-1 clears): used by the
+ * search to time each candidate through the ordinary entry points. */
+li_status li_tune_force(int32_t kernel, int32_t index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LI_H */

@@ -37,6 +37,7 @@ def _load():
         "orc_mm2": ([_i64, _i64, _i64, _i64, _dbl, _dbl, _p, _p, _p, _p, _p, _i64, _p, _p], None),
         "orc_col_mean": ([_i64, _i64, _p, _p], None),
         "orc_col_std": ([_i64, _i64, _p, _p, _p], None),
+        "orc_centred_data": ([_i64, _i64, ctypes.c_int, _dbl, _p, _p, _p, _p], None),
         "orc_covariance": ([_i64, _i64, _p, _p, _p, _p], None),
         "orc_correlation": ([_i64, _i64, _dbl, _p, _p, _p, _p, _p], None),
         "orc_covariance_entries": ([_i64, _i64, _p, _p, _p, _i64, _p], None),
@@ -126,6 +127,21 @@ def col_std(X, mean):
     s = np.empty(M, dtype=np.float64)
     lib.orc_col_std(N, M, _ptr(X), _ptr(mean), _ptr(s))
     return s
+
+
+def centred_data(X, correlation=False, eps=0.1):
+    """(Y, mean, std) -- the data as the covariance (correlation=False) or
+    correlation kernel centres / normalises it, without the contraction;
+    std is None for covariance."""
+    lib = _load()
+    X = _f32(X)
+    N, M = X.shape
+    Y = np.empty((N, M), dtype=np.float64)
+    mean = np.empty(M, dtype=np.float64)
+    std = np.empty(M, dtype=np.float64) if correlation else None
+    lib.orc_centred_data(N, M, 1 if correlation else 0, float(eps), _ptr(X), _ptr(Y), _ptr(mean),
+                         _ptr(std))
+    return Y, mean, std
 
 
 def covariance(X, want_y=True):

@@ -157,6 +157,33 @@ void orc_col_std(int64_t N, int64_t M, const float *X, const double *mean, doubl
 }
 
 /* ------------------------------------------------------------------------
+ * The first steps of the two statistics kernels, without the M x M
+ * contraction: the column means, for correlation the clamped standard
+ * deviations, and the centred (covariance) or normalised (correlation) data
+ * exactly as orc_covariance / orc_correlation below form them.  Used for
+ * checks at sizes where the contraction is too slow to recompute.
+ * ---------------------------------------------------------------------- */
+void orc_centred_data(int64_t N, int64_t M, int correlation, double eps, const float *X,
+                      double *y_out, double *mean, double *stdv)
+{
+    orc_col_mean(N, M, X, mean);
+    if (!correlation) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t j = 0; j < M; ++j) y_out[i * M + j] = (double)X[i * M + j] - mean[j];
+        return;
+    }
+    orc_col_std(N, M, X, mean, stdv);
+    for (int64_t j = 0; j < M; ++j)
+        if (stdv[j] <= eps) stdv[j] = 1.0;
+    double sqn = sqrt((double)N);
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < M; ++j)
+            y_out[i * M + j] = ((double)X[i * M + j] - mean[j]) / (sqn * stdv[j]);
+}
+
+/* ------------------------------------------------------------------------
  * Covariance (Sec. VIII, polybench "covariance"; unbiased divisor N-1):
  *   Y[i][j]     = X[i][j] - mean[j]
  *   cov[a][b]   = (sum_i Y[i][a] * Y[i][b]) / (N - 1)   for a <= b,

@@ -1,0 +1,294 @@
+// Exported C entry points: validate on the host, check the device, pick a
+// tile shape and enqueue the kernels.  Nothing here synchronises.
+#include <hip/hip_runtime_api.h>
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+
+#include "li_internal.h"
+
+namespace li {
+
+li_status hip_fail(int err, const char *what)
+{
+    return fail(LI_ERR_HIP, "%s: HIP error %d (%s)", what, err,
+                hipGetErrorString((hipError_t)err));
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+// 0 = unknown, 1 = gfx950, 2 = unsupported
+std::atomic<int> g_dev_state[kMaxDevices];
+std::atomic<int> g_dev_cus[kMaxDevices];
+
+}  // namespace
+
+li_status ensure_device()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LI_ERR_UNSUPPORTED_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (dev < 0 || dev >= kMaxDevices) return fail(LI_ERR_UNSUPPORTED_DEVICE, "device id %d out of range", dev);
+    int st = g_dev_state[dev].load(std::memory_order_acquire);
+    if (st == 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LI_ERR_UNSUPPORTED_DEVICE, "hipGetDeviceProperties failed (%s)", hipGetErrorString(e));
+        }
+        const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        g_dev_cus[dev].store(prop.multiProcessorCount);
+        st = ok ? 1 : 2;
+        g_dev_state[dev].store(st, std::memory_order_release);
+        if (!ok)
+            return fail(LI_ERR_UNSUPPORTED_DEVICE, "device %d is %s; this library is built for gfx950 only",
+                        dev, prop.gcnArchName);
+    }
+    if (st != 1) return fail(LI_ERR_UNSUPPORTED_DEVICE, "device %d is not gfx950", dev);
+    return LI_OK;
+}
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+    int c = g_dev_cus[dev].load();
+    return c > 0 ? c : 256;
+}
+
+}  // namespace li
+
+using li::Span;
+
+namespace {
+
+// Shared validation of C = alpha*A*B + beta*C.
+li_status validate_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                        const float *B, float beta, float *C, uint64_t *abytes, uint64_t *bbytes,
+                        uint64_t *cbytes)
+{
+    li_status s;
+    if ((s = li::check_nonneg("M", M)) || (s = li::check_nonneg("N", N)) ||
+        (s = li::check_nonneg("K", K)))
+        return s;
+    if (!li::matrix_bytes(M, K, 4, abytes) || !li::matrix_bytes(K, N, 4, bbytes) ||
+        !li::matrix_bytes(M, N, 4, cbytes))
+        return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
+    if (M > 0 && N > 0 && ((M + 63) / 64) * ((N + 63) / 64) > (int64_t)0x7fffffff)
+        return li::fail(LI_ERR_INVALID_SIZE, "too many output tiles");
+    const bool out_any = M > 0 && N > 0;
+    const bool reads_ab = out_any && K > 0 && alpha != 0.f;
+    if (!reads_ab) *abytes = *bbytes = 0;
+    if (!out_any) *cbytes = 0;
+    if ((s = li::check_ptr("A", A, *abytes)) || (s = li::check_ptr("B", B, *bbytes)) ||
+        (s = li::check_ptr("C", C, *cbytes)))
+        return s;
+    (void)beta;
+    if ((s = li::check_no_overlap("C", Span{C, *cbytes}, "A", Span{A, *abytes})) ||
+        (s = li::check_no_overlap("C", Span{C, *cbytes}, "B", Span{B, *bbytes})))
+        return s;
+    return LI_OK;
+}
+
+li_status launched(int err, const char *what)
+{
+    if (err != 0) return li::hip_fail(err, what);
+    return LI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+li_status li_init(void) { return li::ensure_device(); }
+
+li_status li_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A, const float *B,
+                  float beta, float *C, li_stream stream)
+{
+    return li_gemm_ex(M, N, K, alpha, A, B, beta, C, LI_FP32, nullptr, 0, stream);
+}
+
+size_t li_gemm_ex_workspace_bytes(int64_t M, int64_t N, int64_t K, li_precision p)
+{
+    if (M < 0 || N < 0 || K < 0) return 0;
+    if (p == LI_FP32) return 0;
+    if (p != LI_BF16 && p != LI_FP16 && p != LI_BF16X3) return 0;
+    return li::lp_workspace_bytes(M, N, K, (int)p);
+}
+
+li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *A, const float *B,
+                     float beta, float *C, li_precision p, void *workspace, size_t workspace_bytes,
+                     li_stream stream)
+{
+    uint64_t ab, bb, cb;
+    li_status s = validate_gemm(M, N, K, alpha, A, B, beta, C, &ab, &bb, &cb);
+    if (s) return s;
+    if (p != LI_FP32 && p != LI_BF16 && p != LI_FP16 && p != LI_BF16X3)
+        return li::fail(LI_ERR_BAD_ENUM, "unknown precision %d", (int)p);
+    const bool lp = p != LI_FP32 && ab > 0;
+    if (lp) {
+        const size_t need = li::lp_workspace_bytes(M, N, K, (int)p);
+        if (workspace_bytes < need || (need > 0 && workspace == nullptr))
+            return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                            workspace_bytes);
+        const Span ws{workspace, need};
+        if ((s = li::check_no_overlap("workspace", ws, "A", Span{A, ab})) ||
+            (s = li::check_no_overlap("workspace", ws, "B", Span{B, bb})) ||
+            (s = li::check_no_overlap("workspace", ws, "C", Span{C, cb})))
+            return s;
+    }
+    if ((s = li::ensure_device())) return s;
+    if (M == 0 || N == 0) return LI_OK;
+    if (!lp) {
+        const int cfg = li::tune_pick(LI_KERNEL_GEMM_F32, M, N, K);
+        return launched(li::launch_gemm_f32(cfg, M, N, K, alpha, A, K, B, N, beta, C, N, stream),
+                        "gemm_f32 launch");
+    }
+    const int cfg = li::tune_pick(LI_KERNEL_GEMM_LP, M, N, K);
+    return launched(li::launch_gemm_lp(cfg, (int)p, M, N, K, alpha, A, B, beta, C, workspace, stream),
+                    "gemm_lp launch");
+}
+
+li_status li_mm2(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, float alpha, float beta,
+                 const float *A, const float *B, float *tmp, const float *C, float *D,
+                 li_stream stream)
+{
+    li_status s;
+    if ((s = li::check_nonneg("NI", NI)) || (s = li::check_nonneg("NJ", NJ)) ||
+        (s = li::check_nonneg("NK", NK)) || (s = li::check_nonneg("NL", NL)))
+        return s;
+    uint64_t ab, bb, tb, cb, db;
+    if (!li::matrix_bytes(NI, NK, 4, &ab) || !li::matrix_bytes(NK, NJ, 4, &bb) ||
+        !li::matrix_bytes(NI, NJ, 4, &tb) || !li::matrix_bytes(NJ, NL, 4, &cb) ||
+        !li::matrix_bytes(NI, NL, 4, &db))
+        return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
+    // First product writes tmp (NI x NJ); it reads A, B only if it has work.
+    const bool first_reads = NI > 0 && NJ > 0 && NK > 0 && alpha != 0.f;
+    const uint64_t ab_r = first_reads ? ab : 0, bb_r = first_reads ? bb : 0;
+    // Second product reads tmp and C only if NJ > 0 (else D = beta*D).
+    const bool second_reads = NI > 0 && NL > 0 && NJ > 0;
+    const uint64_t cb_r = second_reads ? cb : 0;
+    if ((s = li::check_ptr("A", A, ab_r)) || (s = li::check_ptr("B", B, bb_r)) ||
+        (s = li::check_ptr("tmp", tmp, tb)) || (s = li::check_ptr("C", C, cb_r)) ||
+        (s = li::check_ptr("D", D, db)))
+        return s;
+    const Span sA{A, ab_r}, sB{B, bb_r}, sT{tmp, tb}, sC{C, cb_r}, sD{D, db};
+    if ((s = li::check_no_overlap("tmp", sT, "A", sA)) || (s = li::check_no_overlap("tmp", sT, "B", sB)) ||
+        (s = li::check_no_overlap("tmp", sT, "C", sC)) || (s = li::check_no_overlap("tmp", sT, "D", sD)) ||
+        (s = li::check_no_overlap("D", sD, "A", sA)) || (s = li::check_no_overlap("D", sD, "B", sB)) ||
+        (s = li::check_no_overlap("D", sD, "C", sC)))
+        return s;
+    if ((s = li::ensure_device())) return s;
+    if (NI > 0 && NJ > 0) {
+        const int cfg = li::tune_pick(LI_KERNEL_GEMM_F32, NI, NJ, NK);
+        if ((s = launched(li::launch_gemm_f32(cfg, NI, NJ, NK, alpha, A, NK, B, NJ, 0.f, tmp, NJ, stream),
+                          "mm2 first product launch")))
+            return s;
+    }
+    if (NI > 0 && NL > 0) {
+        const int cfg = li::tune_pick(LI_KERNEL_GEMM_F32, NI, NL, NJ);
+        if ((s = launched(li::launch_gemm_f32(cfg, NI, NL, NJ, 1.f, tmp, NJ, C, NL, beta, D, NL, stream),
+                          "mm2 second product launch")))
+            return s;
+    }
+    return LI_OK;
+}
+
+size_t li_stats_workspace_bytes(int64_t M, int64_t N) { return li::stats_workspace_bytes(M, N); }
+
+}  // extern "C"
+
+namespace {
+
+li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float *data,
+                       float *data_out, double *mean, double *stdv, float *out, void *ws,
+                       size_t ws_bytes, li_stream stream)
+{
+    li_status s;
+    if ((s = li::check_nonneg("M", M)) || (s = li::check_nonneg("N", N))) return s;
+    if (M > 0 && N < (corr ? 1 : 2))
+        return li::fail(LI_ERR_INVALID_SIZE, "%s needs N >= %d samples (got %lld)",
+                        corr ? "correlation" : "covariance", corr ? 1 : 2, (long long)N);
+    if (corr && !(eps >= 0.0)) return li::fail(LI_ERR_INVALID_SIZE, "eps must be >= 0");
+    uint64_t xb, sb, vb = 0;
+    if (!li::matrix_bytes(N, M, 4, &xb) || !li::matrix_bytes(M, M, 4, &sb))
+        return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
+    if (M > 0 && ((M + 63) / 64) * ((M + 63) / 64) > (int64_t)0x7fffffff)
+        return li::fail(LI_ERR_INVALID_SIZE, "too many output tiles");
+    vb = (uint64_t)M * 8;
+    if ((s = li::check_ptr("data", data, xb)) || (s = li::check_ptr("data_out", data_out, xb)) ||
+        (s = li::check_ptr("mean", mean, vb)) ||
+        (s = li::check_ptr(corr ? "corr" : "cov", out, sb)))
+        return s;
+    if (corr && (s = li::check_ptr("stddev", stdv, vb))) return s;
+    const size_t need = li::stats_workspace_bytes(M, N);
+    if (ws_bytes < need || (need > 0 && ws == nullptr))
+        return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    const Span sX{data, xb}, sY{data_out, xb}, sM{mean, vb}, sS{stdv, corr ? vb : 0}, sO{out, sb},
+        sW{ws, need};
+    if (data_out != data && (s = li::check_no_overlap("data_out", sY, "data", sX))) return s;
+    const Span outs[] = {sM, sS, sO, sW};
+    const char *onames[] = {"mean", "stddev", corr ? "corr" : "cov", "workspace"};
+    for (int i = 0; i < 4; ++i) {
+        if ((s = li::check_no_overlap(onames[i], outs[i], "data", sX))) return s;
+        if ((s = li::check_no_overlap(onames[i], outs[i], "data_out", sY))) return s;
+        for (int j = i + 1; j < 4; ++j)
+            if ((s = li::check_no_overlap(onames[i], outs[i], onames[j], outs[j]))) return s;
+    }
+    if ((s = li::ensure_device())) return s;
+    if (M == 0) return LI_OK;
+    if ((s = launched(li::launch_stats(M, N, data, data_out, mean, stdv, corr ? 1 : 0, eps, ws, stream),
+                      "column statistics launch")))
+        return s;
+    const int cfg = li::tune_pick(LI_KERNEL_SYRK_F32, M, M, N);
+    const float scale = corr ? 1.0f : (float)(1.0 / (double)(N - 1));
+    return launched(li::launch_syrk_f32(cfg, M, N, data_out, out, corr ? 1 : 0, scale, stream),
+                    "symmetric contraction launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+li_status li_covariance(int64_t M, int64_t N, const float *data, float *data_out, double *mean,
+                        float *cov, void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    return stats_common(false, M, N, 0.0, data, data_out, mean, nullptr, cov, workspace,
+                        workspace_bytes, stream);
+}
+
+li_status li_correlation(int64_t M, int64_t N, double eps, const float *data, float *data_out,
+                         double *mean, double *stddev, float *corr, void *workspace,
+                         size_t workspace_bytes, li_stream stream)
+{
+    return stats_common(true, M, N, eps, data, data_out, mean, stddev, corr, workspace,
+                        workspace_bytes, stream);
+}
+
+li_status li_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, li_precision p,
+                     li_stream stream)
+{
+    li_status s;
+    if ((s = li::check_nonneg("n", n))) return s;
+    if (p != LI_BF16 && p != LI_FP16) return li::fail(LI_ERR_BAD_ENUM, "precision must be LI_BF16 or LI_FP16");
+    if (p == LI_FP16 && lo != nullptr) return li::fail(LI_ERR_BAD_ENUM, "LI_FP16 has no low part; pass lo = NULL");
+    uint64_t xb, hb;
+    if (!li::matrix_bytes(n, 1, 4, &xb) || !li::matrix_bytes(n, 1, 2, &hb))
+        return li::fail(LI_ERR_INVALID_SIZE, "extent too large");
+    if ((s = li::check_ptr("x", x, xb)) || (s = li::check_ptr("hi", hi, hb))) return s;
+    const Span sX{x, xb}, sH{hi, hb}, sL{lo, lo ? hb : 0};
+    if ((s = li::check_no_overlap("hi", sH, "x", sX)) || (s = li::check_no_overlap("lo", sL, "x", sX)) ||
+        (s = li::check_no_overlap("lo", sL, "hi", sH)))
+        return s;
+    if ((s = li::ensure_device())) return s;
+    if (n == 0) return LI_OK;
+    return launched(li::launch_round16(n, x, hi, lo, (int)p, stream), "round16 launch");
+}
+
+}  // extern "C"

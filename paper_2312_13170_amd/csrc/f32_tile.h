@@ -1,0 +1,261 @@
+// Device building blocks of the FP32 loop-internalised contraction.
+//
+// The reduction loop over k is tiled by BK (loop internalization,
+// Sec. VI-C): each K-tile of both operands is copied from HBM into LDS by the
+// whole work-group, a barrier publishes it, and the inner loop runs on the
+// LDS copy.  Two LDS buffers alternate, so the copy of tile t+1 (issued to
+// registers before the inner loop of tile t) overlaps its arithmetic and one
+// barrier per K-tile suffices.  Accumulation stays in matrix-core
+// accumulator registers for the whole reduction (detect reduction,
+// Sec. VI-B); C is touched once, in the epilogue.
+//
+// Matrix-core step: v_mfma_f32_32x32x2f32 multiplies a 32x2 A block by a
+// 2x32 B block into a 32x32 FP32 accumulator held as 16 floats per lane.
+// Lane l supplies A[l%32][kslot] and B[kslot][l%32] with kslot = l/32; in the
+// accumulator, lane l holds column l%32 and, for register v, row
+// 8*(v/4) + 4*(l/32) + v%4.  Any assignment of real k indices to
+// (step, kslot) pairs is valid as long as A and B agree; here step s of an
+// 8-wide k block uses k = 4*kslot + s, so each lane reads four consecutive
+// k values of a row-major A tile with one 16-byte LDS read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace li {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Workgroups are handed to the 8 XCDs round-robin (id % 8).  Renumber so
+// that each XCD receives one contiguous range of logical tiles: neighbouring
+// tiles share A rows / B columns and then hit in the same XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb)
+{
+    constexpr int NX = 8;
+    const int x = bid % NX, local = bid / NX;
+    const int base = nb / NX, rem = nb % NX;
+    return x * base + (x < rem ? x : rem) + local;
+}
+
+// Logical tile -> (tile row, tile column), column-major inside bands of
+// `group_m` tile rows.
+__device__ __forceinline__ void grouped_tile(int t, int tiles_m, int tiles_n, int group_m,
+                                             int &tm, int &tn)
+{
+    const int per_group = group_m * tiles_n;
+    const int g = t / per_group;
+    const int first = g * group_m;
+    const int gm = min(group_m, tiles_m - first);
+    const int in = t - g * per_group;
+    tm = first + in % gm;
+    tn = in / gm;
+}
+
+// Copies a TR x TC tile of a row-major matrix (rows x cols, leading
+// dimension ld) starting at (r0, c0) to LDS (leading dimension LDL), four
+// consecutive columns per chunk, zero-filling everything outside the matrix.
+// VEC4 requires cols % 4 == 0, ld % 4 == 0 and a 16-byte aligned base.
+template <int TR, int TC, int NT, bool VEC4>
+struct TileLoader {
+    static constexpr int CPR = TC / 4;
+    static constexpr int NCH = TR * CPR;
+    static_assert(TC % 4 == 0, "tile width must be a multiple of 4");
+    static_assert(NCH % NT == 0, "tile chunks must divide evenly among threads");
+    static constexpr int PER = NCH / NT;
+    f32x4 v[PER];
+
+    __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
+                                         int64_t cols, int64_t r0, int64_t c0, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid + i * NT;
+            const int r = c / CPR, cc = (c % CPR) * 4;
+            const int64_t gr = r0 + r, gc = c0 + cc;
+            if (VEC4) {
+                if (gr < rows && gc < cols)
+                    v[i] = *reinterpret_cast<const f32x4 *>(p + gr * ld + gc);
+                else
+                    v[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            } else {
+                const bool rok = gr < rows;
+                const float *q = p + gr * ld + gc;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[i][e] = (rok && gc + e < cols) ? q[e] : 0.f;
+            }
+        }
+    }
+
+    template <int LDL>
+    __device__ __forceinline__ void store(float *lds, int tid) const
+    {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid + i * NT;
+            const int r = c / CPR, cc = (c % CPR) * 4;
+            *reinterpret_cast<f32x4 *>(lds + r * LDL + cc) = v[i];
+        }
+    }
+};
+
+// One work-group computes a BM x BN block tile with WM x WN waves; each wave
+// owns a (BM/WM) x (BN/WN) sub-tile made of TM x TN 32x32 accumulator blocks.
+// A_KMAJOR: A element (m, k) is at A[k*lda + m] (the transposed operand of
+// the symmetric contraction); otherwise at A[m*lda + k].  B element (k, n)
+// is always at B[k*ldb + n].
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, bool VEC4>
+struct F32Tile {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
+    static_assert(TM >= 1 && TN >= 1 && BM % (32 * WM) == 0 && BN % (32 * WN) == 0, "bad wave tiling");
+    static_assert(BK % 8 == 0, "BK must be a multiple of 8");
+    // LDS layouts.  Row-major A: [BM][BK+4] (16-byte reads of 4 k values;
+    // the +4 pad puts 8 consecutive rows on distinct bank groups).  K-major
+    // operands: [BK][B?+8] (lanes read consecutive m / n of one k row).
+    static constexpr int A_LD = A_KMAJOR ? BM + 8 : BK + 4;
+    static constexpr int A_STAGE = (A_KMAJOR ? BK : BM) * A_LD;
+    static constexpr int B_LD = BN + 8;
+    static constexpr int B_STAGE = BK * B_LD;
+    static constexpr int LDS_FLOATS = 2 * (A_STAGE + B_STAGE);
+
+    using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, VEC4>;
+    using BLoader = TileLoader<BK, BN, NT, VEC4>;
+
+    __device__ __forceinline__ static void zero(f32x16 (&acc)[TM][TN])
+    {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+    }
+
+    __device__ __forceinline__ static void load_a(ALoader &la, const float *A, int64_t lda,
+                                                  int64_t M, int64_t kend, int64_t m0, int64_t k0,
+                                                  int tid)
+    {
+        if (A_KMAJOR)
+            la.load(A, lda, kend, M, k0, m0, tid);
+        else
+            la.load(A, lda, M, kend, m0, k0, tid);
+    }
+
+    // Inner loop over one LDS K-tile.
+    __device__ __forceinline__ static void compute(const float *As, const float *Bs,
+                                                   f32x16 (&acc)[TM][TN], int wm0, int wn0,
+                                                   int lane)
+    {
+        const int l32 = lane & 31, h4 = (lane >> 5) * 4;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 8) {
+            float a[TM][4], b[TN][4];
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                if (!A_KMAJOR) {
+                    const f32x4 t = *reinterpret_cast<const f32x4 *>(
+                        As + (wm0 + 32 * tm + l32) * A_LD + kk + h4);
+                    a[tm][0] = t[0];
+                    a[tm][1] = t[1];
+                    a[tm][2] = t[2];
+                    a[tm][3] = t[3];
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) a[tm][s] = As[(kk + h4 + s) * A_LD + wm0 + 32 * tm + l32];
+                }
+            }
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) b[tn][s] = Bs[(kk + h4 + s) * B_LD + wn0 + 32 * tn + l32];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < TN; ++tn)
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[tm][s], b[tn][s],
+                                                                           acc[tm][tn], 0, 0, 0);
+        }
+    }
+
+    // Full reduction over k in [kbeg, kend) for the block tile at (m0, n0).
+    // Must be reached by every thread of the work-group (it contains
+    // barriers); the trip count depends only on uniform values.
+    __device__ __forceinline__ static void mainloop(float *lds, const float *A, int64_t lda,
+                                                    const float *B, int64_t ldb, int64_t M,
+                                                    int64_t N, int64_t kbeg, int64_t kend,
+                                                    int64_t m0, int64_t n0, f32x16 (&acc)[TM][TN])
+    {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+        float *As = lds;
+        float *Bs = lds + 2 * A_STAGE;
+        const int64_t nk = (kend - kbeg + BK - 1) / BK;
+        if (nk <= 0) return;
+        ALoader la;
+        BLoader lb;
+        load_a(la, A, lda, M, kend, m0, kbeg, tid);
+        lb.load(B, ldb, kend, N, kbeg, n0, tid);
+        la.template store<A_LD>(As, tid);
+        lb.template store<B_LD>(Bs, tid);
+        __syncthreads();
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int cur = (int)(kt & 1);
+            const bool more = kt + 1 < nk;
+            if (more) {
+                const int64_t k1 = kbeg + (kt + 1) * BK;
+                load_a(la, A, lda, M, kend, m0, k1, tid);
+                lb.load(B, ldb, kend, N, k1, n0, tid);
+            }
+            compute(As + cur * A_STAGE, Bs + cur * B_STAGE, acc, wm0, wn0, lane);
+            if (more) {
+                la.template store<A_LD>(As + (cur ^ 1) * A_STAGE, tid);
+                lb.template store<B_LD>(Bs + (cur ^ 1) * B_STAGE, tid);
+            }
+            __syncthreads();
+        }
+    }
+
+    // Row / column of accumulator element v of block (tm, tn) in the tile.
+    __device__ __forceinline__ static int acc_row(int wm0, int tm, int v, int lane)
+    {
+        return wm0 + 32 * tm + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    }
+    __device__ __forceinline__ static int acc_col(int wn0, int tn, int lane)
+    {
+        return wn0 + 32 * tn + (lane & 31);
+    }
+
+    // C = alpha*acc + beta*C over the in-range part of the tile.
+    __device__ __forceinline__ static void epilogue_gemm(const f32x16 (&acc)[TM][TN], float *C,
+                                                         int64_t ldc, int64_t M, int64_t N,
+                                                         int64_t m0, int64_t n0, float alpha,
+                                                         float beta)
+    {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                const int64_t col = n0 + acc_col(wn0, tn, lane);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = m0 + acc_row(wm0, tm, v, lane);
+                    if (row < M && col < N) {
+                        float *c = C + row * ldc + col;
+                        float r = alpha * acc[tm][tn][v];
+                        if (beta != 0.f) r += beta * *c;
+                        *c = r;
+                    }
+                }
+            }
+    }
+};
+
+}  // namespace li

@@ -1,0 +1,437 @@
+// Reduced-precision GEMM on the gfx950 matrix cores: bf16 and fp16 operands
+// with FP32 accumulation, and the split-bf16 three-product scheme.
+//
+// Two steps, both on the caller's stream:
+//  1. Rounding pre-pass (HBM-bound).  A (M x K) is rounded row by row into
+//     Ah[Mp][Kp]; B (K x N) is rounded and transposed into Bh[Np][Kp], so
+//     both operands are k-contiguous, the layout the 32x32x16 matrix-core
+//     step reads with one 16-byte LDS load per lane.  For split-bf16 the
+//     residuals Al = bf16(A - Ah), Bl = bf16(B - Bh) are written beside
+//     them; A - Ah is exact in FP32 (Sterbenz).  Mp, Np are padded to
+//     multiples of 256 and Kp to a multiple of 64 with zeros, so the main
+//     loop needs no bounds checks.
+//  2. Loop-internalised GEMM (Sec. VI-C): K-tiles of every operand term go
+//     through double-buffered LDS, accumulation stays in matrix-core
+//     registers, C = alpha*acc + beta*C once at the end.
+//
+// v_mfma_f32_32x32x16_{bf16,f16}: lane l supplies 8 consecutive k values of
+// row l%32 of A and of column l%32 of B (lane half l/32 selects which 8 of
+// the 16); the accumulator layout is that of the FP32 32x32 step.
+//
+// LDS rows are BK elements (64 or 128 bytes, i.e. CPR 16-byte chunks).  The
+// chunk index is XOR-swizzled with the row so that the 16-byte reads of 16
+// consecutive rows at one logical chunk fall into distinct bank groups:
+//   CPR = 8: phys = c ^ ((r ^ (r >> 3)) & 7)
+//   CPR = 4: phys = c ^ (((r >> 1) ^ (r >> 3)) & 3)
+#include <hip/hip_runtime.h>
+
+#include "li_internal.h"
+#include "tiles.h"
+
+namespace li {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int64_t kPadMN = 256;
+constexpr int64_t kPadK = 64;
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// ---------------------------------------------------------------- rounding
+// float -> bfloat16 bits, round to nearest even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x0040u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
+
+// float -> binary16 bits via the hardware conversion (round to nearest even
+// in the default mode, gradual underflow, overflow to infinity).
+__device__ __forceinline__ uint32_t fp16_bits(float x)
+{
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
+// hi / lo parts of one value for precision prec (1 bf16, 2 fp16, 3 split bf16)
+__device__ __forceinline__ void split_value(float x, int prec, uint32_t &hi, uint32_t &lo)
+{
+    if (prec == 2) {
+        hi = fp16_bits(x);
+        lo = 0;
+        return;
+    }
+    hi = bf16_bits(x);
+    lo = prec == 3 ? bf16_bits(x - bf16_value(hi)) : 0u;
+}
+
+__global__ __launch_bounds__(256) void round16_kernel(const float *__restrict__ x, int64_t n,
+                                                      uint16_t *__restrict__ hi,
+                                                      uint16_t *__restrict__ lo, int prec)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t h, l;
+        split_value(x[i], lo ? 3 : prec, h, l);
+        hi[i] = (uint16_t)h;
+        if (lo) lo[i] = (uint16_t)l;
+    }
+}
+
+// A (M x K, row-major FP32) -> hi/lo [Mp][Kp], zero padded.  One thread
+// writes 8 consecutive k of one row (16 bytes per output array).
+__global__ __launch_bounds__(256) void round_rows_kernel(const float *__restrict__ A, int64_t M,
+                                                         int64_t K, int64_t Mp, int64_t Kp,
+                                                         uint16_t *__restrict__ hi,
+                                                         uint16_t *__restrict__ lo, int prec,
+                                                         int vec4)
+{
+    const int64_t cpr = Kp / 8;
+    const int64_t total = Mp * cpr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
+        const int64_t r = c / cpr, k0 = (c % cpr) * 8;
+        float v[8];
+        if (r < M && vec4 && k0 + 8 <= K) {
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(A + r * K + k0);
+            const f32x4 b = *reinterpret_cast<const f32x4 *>(A + r * K + k0 + 4);
+            v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+            v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (r < M && k0 + e < K) ? A[r * K + k0 + e] : 0.f;
+        }
+        u32x4 ph, pl;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint32_t h0, l0, h1, l1;
+            split_value(v[2 * e], prec, h0, l0);
+            split_value(v[2 * e + 1], prec, h1, l1);
+            ph[e] = h0 | (h1 << 16);
+            pl[e] = l0 | (l1 << 16);
+        }
+        *reinterpret_cast<u32x4 *>(hi + r * Kp + k0) = ph;
+        if (prec == 3) *reinterpret_cast<u32x4 *>(lo + r * Kp + k0) = pl;
+    }
+}
+
+// B (K x N, row-major FP32) -> hi/lo [Np][Kp] (transposed), zero padded.
+// 64 x 64 tiles through LDS: coalesced reads along n, coalesced writes
+// along k.
+__global__ __launch_bounds__(256) void round_transpose_kernel(const float *__restrict__ B,
+                                                              int64_t K, int64_t N, int64_t Np,
+                                                              int64_t Kp, uint16_t *__restrict__ hi,
+                                                              uint16_t *__restrict__ lo, int prec)
+{
+    __shared__ float t[64][65];
+    const int64_t n0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = tid + i * 256;
+        const int kr = e / 64, nc = e % 64;
+        const int64_t gk = k0 + kr, gn = n0 + nc;
+        t[kr][nc] = (gk < K && gn < N) ? B[gk * N + gn] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = tid + i * 256;
+        const int nr = e / 8, kc = (e % 8) * 8;
+        u32x4 ph, pl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t h0, l0, h1, l1;
+            split_value(t[kc + 2 * q][nr], prec, h0, l0);
+            split_value(t[kc + 2 * q + 1][nr], prec, h1, l1);
+            ph[q] = h0 | (h1 << 16);
+            pl[q] = l0 | (l1 << 16);
+        }
+        const int64_t off = (n0 + nr) * Kp + k0 + kc;
+        *reinterpret_cast<u32x4 *>(hi + off) = ph;
+        if (prec == 3) *reinterpret_cast<u32x4 *>(lo + off) = pl;
+    }
+    (void)Np;
+}
+
+// ---------------------------------------------------------------- GEMM
+__device__ __forceinline__ int xcd_remap_lp(int bid, int nb)
+{
+    constexpr int NX = 8;
+    const int x = bid % NX, local = bid / NX;
+    const int base = nb / NX, rem = nb % NX;
+    return x * base + (x < rem ? x : rem) + local;
+}
+
+template <int CPR>
+__device__ __forceinline__ int swz(int r, int c)
+{
+    if (CPR == 8) return c ^ ((r ^ (r >> 3)) & 7);
+    return c ^ (((r >> 1) ^ (r >> 3)) & 3);
+}
+
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int TERMS, bool FP16>
+struct LpTile {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
+    static constexpr int CPR = BK / 8;  // 16-byte chunks per LDS row
+    static constexpr int PARTS = TERMS == 3 ? 2 : 1;
+    static constexpr int NTERMS = TERMS;
+    static constexpr bool IS_FP16 = FP16;
+    static constexpr int A_ELEMS = BM * BK, B_ELEMS = BN * BK;
+    static constexpr int STAGE = PARTS * (A_ELEMS + B_ELEMS);  // bf16 elements
+    static constexpr int LDS_ELEMS = 2 * STAGE;
+    static constexpr int A_CH = BM * CPR / NT, B_CH = BN * CPR / NT;
+    static_assert(CPR == 4 || CPR == 8, "BK must be 32 or 64");
+    static_assert((BM * CPR) % NT == 0 && (BN * CPR) % NT == 0, "chunks must divide among threads");
+    static_assert(TM >= 1 && TN >= 1, "bad wave tiling");
+    static_assert(kPadMN % BM == 0 && kPadMN % BN == 0 && kPadK % BK == 0, "tile must divide padding");
+};
+
+template <class T>
+__global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restrict__ Ah,
+                                                        const uint16_t *__restrict__ Al,
+                                                        const uint16_t *__restrict__ Bh,
+                                                        const uint16_t *__restrict__ Bl,
+                                                        int64_t Kp, float *__restrict__ C,
+                                                        int64_t M, int64_t N, float alpha,
+                                                        float beta, int tiles_m, int tiles_n,
+                                                        int group_m)
+{
+    constexpr int BM = T::BM, BN = T::BN, BK = T::BK, NT = T::NT, CPR = T::CPR;
+    constexpr int TM = T::TM, TN = T::TN, PARTS = T::PARTS;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[T::LDS_ELEMS];
+
+    const int nb = tiles_m * tiles_n;
+    const int t = xcd_remap_lp(blockIdx.x, nb);
+    const int per_group = group_m * tiles_n;
+    const int g = t / per_group;
+    const int first = g * group_m;
+    const int gm = min(group_m, tiles_m - first);
+    const int in = t - g * per_group;
+    const int tmi = first + in % gm, tni = in / gm;
+    const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave / T::WN) * (BM / T::WM), wn0 = (wave % T::WN) * (BN / T::WN);
+    const int l32 = lane & 31, hsel = lane >> 5;
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    // LDS stage layout: [A parts][B parts], each part rows x BK, swizzled.
+    const uint16_t *srcA[2] = {Ah + m0 * Kp, Al ? Al + m0 * Kp : nullptr};
+    const uint16_t *srcB[2] = {Bh + n0 * Kp, Bl ? Bl + n0 * Kp : nullptr};
+    u32x4 ra[PARTS][T::A_CH], rb[PARTS][T::B_CH];
+
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int p = 0; p < PARTS; ++p) {
+#pragma unroll
+            for (int i = 0; i < T::A_CH; ++i) {
+                const int c = tid + i * NT;
+                const int r = c / CPR, cc = c % CPR;
+                ra[p][i] = *reinterpret_cast<const u32x4 *>(srcA[p] + r * Kp + k0 + cc * 8);
+            }
+#pragma unroll
+            for (int i = 0; i < T::B_CH; ++i) {
+                const int c = tid + i * NT;
+                const int r = c / CPR, cc = c % CPR;
+                rb[p][i] = *reinterpret_cast<const u32x4 *>(srcB[p] + r * Kp + k0 + cc * 8);
+            }
+        }
+    };
+    auto sstore = [&](uint16_t *stage) {
+#pragma unroll
+        for (int p = 0; p < PARTS; ++p) {
+            uint16_t *As = stage + p * T::A_ELEMS;
+            uint16_t *Bs = stage + PARTS * T::A_ELEMS + p * T::B_ELEMS;
+#pragma unroll
+            for (int i = 0; i < T::A_CH; ++i) {
+                const int c = tid + i * NT;
+                const int r = c / CPR, cc = c % CPR;
+                *reinterpret_cast<u32x4 *>(As + r * BK + swz<CPR>(r, cc) * 8) = ra[p][i];
+            }
+#pragma unroll
+            for (int i = 0; i < T::B_CH; ++i) {
+                const int c = tid + i * NT;
+                const int r = c / CPR, cc = c % CPR;
+                *reinterpret_cast<u32x4 *>(Bs + r * BK + swz<CPR>(r, cc) * 8) = rb[p][i];
+            }
+        }
+    };
+
+    const int64_t nk = Kp / BK;
+    gload(0);
+    sstore(lds);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        uint16_t *stage = lds + (kt & 1) * T::STAGE;
+        const bool more = kt + 1 < nk;
+        if (more) gload((kt + 1) * BK);
+        const uint16_t *As = stage;
+        const uint16_t *Bs = stage + PARTS * T::A_ELEMS;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const int cidx = kk / 8 + hsel;
+            u32x4 fa[PARTS][TM], fb[PARTS][TN];
+#pragma unroll
+            for (int p = 0; p < PARTS; ++p) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wm0 + 32 * i + l32;
+                    fa[p][i] = *reinterpret_cast<const u32x4 *>(As + p * T::A_ELEMS + r * BK + swz<CPR>(r, cidx) * 8);
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int r = wn0 + 32 * j + l32;
+                    fb[p][j] = *reinterpret_cast<const u32x4 *>(Bs + p * T::B_ELEMS + r * BK + swz<CPR>(r, cidx) * 8);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if (T::IS_FP16) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8, fa[0][i]), __builtin_bit_cast(f16x8, fb[0][j]),
+                            acc[i][j], 0, 0, 0);
+                    } else {
+                        if (T::NTERMS == 3) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, fa[1][i]), __builtin_bit_cast(bf16x8, fb[0][j]),
+                                acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                __builtin_bit_cast(bf16x8, fa[0][i]), __builtin_bit_cast(bf16x8, fb[PARTS - 1][j]),
+                                acc[i][j], 0, 0, 0);
+                        }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, fa[0][i]), __builtin_bit_cast(bf16x8, fb[0][j]),
+                            acc[i][j], 0, 0, 0);
+                    }
+                }
+        }
+        if (more) sstore(lds + ((kt + 1) & 1) * T::STAGE);
+        __syncthreads();
+    }
+
+    // C = alpha*acc + beta*C over the in-range part of the tile.
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t col = n0 + wn0 + 32 * j + l32;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = m0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                if (row < M && col < N) {
+                    float *c = C + row * N + col;
+                    float r = alpha * acc[i][j][v];
+                    if (beta != 0.f) r += beta * *c;
+                    *c = r;
+                }
+            }
+        }
+}
+
+struct LpLayout {
+    int64_t Mp, Np, Kp;
+    uint16_t *Ah, *Al, *Bh, *Bl;
+};
+
+LpLayout lp_layout(int64_t M, int64_t N, int64_t K, int prec, void *ws)
+{
+    LpLayout L;
+    L.Mp = round_up(M > 0 ? M : 1, kPadMN);
+    L.Np = round_up(N > 0 ? N : 1, kPadMN);
+    L.Kp = round_up(K > 0 ? K : 1, kPadK);
+    uint16_t *p = (uint16_t *)ws;
+    L.Ah = p;
+    p += L.Mp * L.Kp;
+    L.Al = nullptr;
+    if (prec == 3) {
+        L.Al = p;
+        p += L.Mp * L.Kp;
+    }
+    L.Bh = p;
+    p += L.Np * L.Kp;
+    L.Bl = nullptr;
+    if (prec == 3) L.Bl = p;
+    return L;
+}
+
+template <class T>
+int run_lp(const LpLayout &L, int64_t M, int64_t N, float alpha, float beta, float *C,
+           hipStream_t s)
+{
+    const int tiles_m = (int)((M + T::BM - 1) / T::BM);
+    const int tiles_n = (int)((N + T::BN - 1) / T::BN);
+    hipLaunchKernelGGL(gemm_lp_kernel<T>, dim3(tiles_m * tiles_n), dim3(T::NT), 0, s, L.Ah, L.Al,
+                       L.Bh, L.Bl, L.Kp, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+size_t lp_workspace_bytes(int64_t M, int64_t N, int64_t K, int prec)
+{
+    const int64_t Mp = round_up(M > 0 ? M : 1, kPadMN), Np = round_up(N > 0 ? N : 1, kPadMN);
+    const int64_t Kp = round_up(K > 0 ? K : 1, kPadK);
+    const int64_t parts = prec == 3 ? 2 : 1;
+    return (size_t)((Mp + Np) * Kp * parts * 2);
+}
+
+int launch_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, int prec, void *stream)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(round16_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, x,
+                       n, hi, lo, prec);
+    return (int)hipGetLastError();
+}
+
+int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                   const float *B, float beta, float *C, void *ws, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const LpLayout L = lp_layout(M, N, K, prec, ws);
+    {
+        const int vec4 = (K % 4 == 0) && (((uintptr_t)A & 15) == 0);
+        int64_t blocks = (L.Mp * (L.Kp / 8) + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL(round_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, M, K, L.Mp,
+                           L.Kp, L.Ah, L.Al, prec, vec4);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(round_transpose_kernel, dim3((unsigned)(L.Np / 64), (unsigned)(L.Kp / 64)),
+                           dim3(256), 0, s, B, K, N, L.Np, L.Kp, L.Bh, L.Bl, prec);
+        e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+    }
+    switch (cfg) {
+#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK)                                                      \
+    case IDX:                                                                                     \
+        if (prec == 3) return run_lp<LpTile<BM, BN, (BK > 32 ? 32 : BK), WM, WN, 3, false>>(L, M, N, alpha, beta, C, s); \
+        if (prec == 2) return run_lp<LpTile<BM, BN, BK, WM, WN, 1, true>>(L, M, N, alpha, beta, C, s); \
+        return run_lp<LpTile<BM, BN, BK, WM, WN, 1, false>>(L, M, N, alpha, beta, C, s);
+        LI_GEMM_LP_CANDIDATES(LI_CASE)
+#undef LI_CASE
+    default:
+        return (int)hipErrorInvalidValue;
+    }
+}
+
+}  // namespace li

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host-side translation units of libli.
+// No device code here; kernels live in the .hip files and are reached through
+// the launcher functions declared below.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "li.h"
+
+namespace li {
+
+// ---------------------------------------------------------------- errors
+// Records a message for li_last_error() and returns `s`.
+li_status fail(li_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// ---------------------------------------------------------------- validation
+// (validate.cpp: plain C++, no HIP headers, so it is testable without a GPU)
+struct Span {
+    const void *p;
+    uint64_t bytes;
+};
+// bytes of an r x c matrix of `elem`-byte elements; false if it overflows the
+// supported range (2^56 bytes).
+bool matrix_bytes(int64_t r, int64_t c, int64_t elem, uint64_t *out);
+bool overlaps(Span a, Span b);
+li_status check_nonneg(const char *what, int64_t v);
+li_status check_ptr(const char *what, const void *p, uint64_t bytes);
+li_status check_no_overlap(const char *out_name, Span out, const char *in_name, Span in);
+
+// ---------------------------------------------------------------- device
+li_status ensure_device();   // gfx950 check for the current device
+int device_cu_count();       // compute units of the current device
+
+// ---------------------------------------------------------------- tuning
+struct TileCfg {
+    int bm, bn, bk, wm, wn, split_k;
+};
+int tune_num(int kernel);
+const TileCfg &tune_cfg(int kernel, int idx);
+// candidate index for a problem: forced > table > built-in heuristic
+int tune_pick(int kernel, int64_t M, int64_t N, int64_t K);
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return the hipError_t (as int) of the
+// launch; sizes are already validated.
+//
+// FP32 matrix-core GEMM on row-major operands:
+//   C[MxN] = alpha * A[MxK] * B[KxN] + beta * C
+int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                    int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
+                    void *stream);
+
+// Symmetric contraction S = Y^T Y (Y: N x M row-major), upper block tiles
+// computed and mirrored.  mode 0: S *= scale (covariance); mode 1: diagonal
+// forced to 1.0 (correlation).
+int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode,
+                    float scale, void *stream);
+
+// Column statistics (FP64) and centring / normalisation.
+size_t stats_workspace_bytes(int64_t M, int64_t N);
+int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
+                 int correlation, double eps, void *ws, void *stream);
+
+// Reduced-precision path
+size_t lp_workspace_bytes(int64_t M, int64_t N, int64_t K, int prec);
+int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alpha,
+                   const float *A, const float *B, float beta, float *C, void *ws,
+                   void *stream);
+int launch_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, int prec,
+                   void *stream);
+
+}  // namespace li

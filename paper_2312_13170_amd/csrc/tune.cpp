@@ -1,0 +1,163 @@
+// Tile-shape tuning table.  Each kernel family has a fixed list of compiled
+// tile shapes (tiles.h).  For every (family, size bucket) the table holds the
+// candidate to use; unset entries fall back to a built-in heuristic.  A
+// "forced" candidate overrides everything for one family: the search
+// (autotune.py) forces each candidate in turn and times the ordinary entry
+// points with HIP events, then writes the winners back with li_tune_set.
+#include <atomic>
+
+#include "li_internal.h"
+#include "tiles.h"
+
+namespace li {
+namespace {
+
+#define LI_ENTRY(IDX, BM, BN, BK, WM, WN, SK) {BM, BN, BK, WM, WN, SK},
+const TileCfg kGemmF32[] = {LI_GEMM_F32_CANDIDATES(LI_ENTRY)};
+const TileCfg kSyrkF32[] = {LI_SYRK_F32_CANDIDATES(LI_ENTRY)};
+const TileCfg kGemmLp[] = {LI_GEMM_LP_CANDIDATES(LI_ENTRY)};
+#undef LI_ENTRY
+
+constexpr int kFamilies = 3;
+constexpr int kBuckets = 64;
+
+const TileCfg *family(int k, int *n)
+{
+    switch (k) {
+    case LI_KERNEL_GEMM_F32:
+        *n = (int)(sizeof(kGemmF32) / sizeof(kGemmF32[0]));
+        return kGemmF32;
+    case LI_KERNEL_SYRK_F32:
+        *n = (int)(sizeof(kSyrkF32) / sizeof(kSyrkF32[0]));
+        return kSyrkF32;
+    case LI_KERNEL_GEMM_LP:
+        *n = (int)(sizeof(kGemmLp) / sizeof(kGemmLp[0]));
+        return kGemmLp;
+    default:
+        *n = 0;
+        return nullptr;
+    }
+}
+
+// Entries hold candidate index + 1; the static zero-initialisation therefore
+// means "unset" without any start-up code.
+std::atomic<int> g_table[kFamilies][kBuckets];
+std::atomic<int> g_forced[kFamilies];
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Built-in choice: the largest tile that still gives at least one tile per
+// compute unit (256 on MI355X), else the smallest.
+int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
+{
+    (void)K;
+    const int64_t cus = 256;
+    if (kernel == LI_KERNEL_GEMM_F32) {
+        if (ceil_div(M, 128) * ceil_div(N, 128) >= cus) return 0;
+        if (ceil_div(M, 128) * ceil_div(N, 64) >= cus) return 3;
+        return 2;
+    }
+    if (kernel == LI_KERNEL_SYRK_F32) {
+        const int64_t t128 = ceil_div(M, 128);
+        if (t128 * (t128 + 1) / 2 >= cus) return 0;
+        return 2;
+    }
+    if (kernel == LI_KERNEL_GEMM_LP) {
+        if (ceil_div(M, 256) * ceil_div(N, 256) >= cus) return 0;
+        if (ceil_div(M, 128) * ceil_div(N, 128) >= cus / 2) return 1;
+        return 4;
+    }
+    return 0;
+}
+
+}  // namespace
+
+int tune_num(int kernel)
+{
+    int n;
+    family(kernel, &n);
+    return n;
+}
+
+const TileCfg &tune_cfg(int kernel, int idx)
+{
+    int n;
+    return family(kernel, &n)[idx];
+}
+
+int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
+{
+    const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
+    if (f >= 0) return f;
+    const int b = li_tune_bucket(M, N, K);
+    const int t = g_table[kernel][b].load(std::memory_order_relaxed) - 1;
+    if (t >= 0) return t;
+    return heuristic(kernel, M, N, K);
+}
+
+}  // namespace li
+
+extern "C" {
+
+int32_t li_tune_num_candidates(int32_t kernel) { return li::tune_num(kernel); }
+
+li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out)
+{
+    int n;
+    const li::TileCfg *f = li::family(kernel, &n);
+    if (!f) return li::fail(LI_ERR_BAD_ENUM, "unknown kernel family %d", kernel);
+    if (index < 0 || index >= n)
+        return li::fail(LI_ERR_NOT_FOUND, "candidate %d out of range [0, %d)", index, n);
+    if (!out) return li::fail(LI_ERR_NULL_POINTER, "out is NULL");
+    out->bm = f[index].bm;
+    out->bn = f[index].bn;
+    out->bk = f[index].bk;
+    out->waves_m = f[index].wm;
+    out->waves_n = f[index].wn;
+    out->split_k = f[index].split_k;
+    return LI_OK;
+}
+
+int32_t li_tune_bucket(int64_t M, int64_t N, int64_t K)
+{
+    int64_t m = M;
+    if (N > m) m = N;
+    if (K > m) m = K;
+    int b = 0;
+    while (m > 0 && b < 63) {
+        m >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+li_status li_tune_set(int32_t kernel, int32_t bucket, int32_t index)
+{
+    int n;
+    if (!li::family(kernel, &n)) return li::fail(LI_ERR_BAD_ENUM, "unknown kernel family %d", kernel);
+    if (bucket < 0 || bucket >= li::kBuckets)
+        return li::fail(LI_ERR_INVALID_SIZE, "bucket %d out of range", bucket);
+    if (index < -1 || index >= n)
+        return li::fail(LI_ERR_NOT_FOUND, "candidate %d out of range [-1, %d)", index, n);
+    li::g_table[kernel][bucket].store(index + 1);
+    return LI_OK;
+}
+
+int32_t li_tune_get(int32_t kernel, int32_t bucket)
+{
+    int n;
+    if (!li::family(kernel, &n) || bucket < 0 || bucket >= li::kBuckets) return -1;
+    return li::g_table[kernel][bucket].load() - 1;
+}
+
+li_status li_tune_force(int32_t kernel, int32_t index)
+{
+    int n;
+    if (!li::family(kernel, &n)) return li::fail(LI_ERR_BAD_ENUM, "unknown kernel family %d", kernel);
+    if (index < -1 || index >= n)
+        return li::fail(LI_ERR_NOT_FOUND, "candidate %d out of range [-1, %d)", index, n);
+    li::g_forced[kernel].store(index + 1);
+    return LI_OK;
+}
+
+}  // extern "C"

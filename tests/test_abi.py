@@ -1,0 +1,124 @@
+"""The C ABI on the host: the library loads, exports every entry point that
+include/li.h declares, and rejects invalid arguments before touching the GPU
+(every call here fails validation, so no HIP work is issued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "li.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(li_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def li():
+    from paper_2312_13170_amd import li as mod
+    return mod
+
+
+def test_header_declares_entry_points():
+    syms = _declared_symbols()
+    for s in ["li_gemm", "li_gemm_ex", "li_mm2", "li_covariance", "li_correlation",
+              "li_group_plan_create", "li_group_plan_launch", "li_tune_set", "li_last_error"]:
+        assert s in syms
+
+
+def test_every_declared_symbol_is_exported(li):
+    lib = ctypes.CDLL(li.LIB_PATH)
+    for s in _declared_symbols():
+        assert hasattr(lib, s), s
+    assert set(_declared_symbols()) == set(li.EXPORTED)
+
+
+def test_version(li):
+    assert "gfx950" in li.li_version()
+
+
+FAKE = 1 << 40  # a host integer used as a device address; never dereferenced
+
+
+def _status(li, fn, *args):
+    return fn(*args)
+
+
+def test_negative_sizes_rejected(li):
+    lib = li._lib
+    assert lib.li_gemm(-1, 4, 4, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, None) == li.LI_ERR_INVALID_SIZE
+    assert "M" in li.li_last_error()
+    assert lib.li_mm2(4, -2, 4, 4, 1.0, 0.0, FAKE, FAKE, FAKE, FAKE, FAKE, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_covariance(-3, 8, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 20, None) == li.LI_ERR_INVALID_SIZE
+
+
+def test_null_pointers_rejected(li):
+    lib = li._lib
+    assert lib.li_gemm(4, 4, 4, 1.0, None, FAKE, 0.0, FAKE + 4096, None) == li.LI_ERR_NULL_POINTER
+    assert lib.li_gemm(4, 4, 4, 1.0, FAKE, FAKE + 4096, 0.0, None, None) == li.LI_ERR_NULL_POINTER
+    assert "C" in li.li_last_error()
+
+
+def test_overlap_rejected(li):
+    lib = li._lib
+    # C (64x64 floats) starts inside A
+    assert lib.li_gemm(64, 64, 64, 1.0, FAKE, FAKE + (1 << 20), 0.0, FAKE + 100, None) == li.LI_ERR_OVERLAP
+    # mm2: D overlapping tmp
+    n = 16
+    b = 4 * n * n
+    st = lib.li_mm2(n, n, n, n, 1.0, 1.0, FAKE, FAKE + b, FAKE + 2 * b, FAKE + 3 * b, FAKE + 2 * b + 8, None)
+    assert st == li.LI_ERR_OVERLAP
+
+
+def test_covariance_argument_rules(li):
+    lib = li._lib
+    M, N = 8, 16
+    xb = 4 * M * N
+    ws = lib.li_stats_workspace_bytes(M, N)
+    assert ws > 0
+    # N < 2 is undefined for the unbiased covariance
+    assert lib.li_covariance(M, 1, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 3 * xb, FAKE + 4 * xb, ws, None) == li.LI_ERR_INVALID_SIZE
+    # workspace too small
+    assert lib.li_covariance(M, N, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 3 * xb, FAKE + 4 * xb, ws - 8, None) == li.LI_ERR_WORKSPACE
+    # data_out partially overlapping data
+    assert lib.li_covariance(M, N, FAKE, FAKE + 4, FAKE + 2 * xb, FAKE + 3 * xb, FAKE + 4 * xb, ws, None) == li.LI_ERR_OVERLAP
+    # mean overlapping cov
+    assert lib.li_covariance(M, N, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 2 * xb + 8, FAKE + 4 * xb, ws, None) == li.LI_ERR_OVERLAP
+    # correlation: negative eps
+    assert lib.li_correlation(M, N, -0.1, FAKE, FAKE, FAKE + 2 * xb, FAKE + 3 * xb, FAKE + 4 * xb,
+                              FAKE + 8 * xb, ws, None) == li.LI_ERR_INVALID_SIZE
+
+
+def test_precision_enum_and_workspace(li):
+    lib = li._lib
+    assert lib.li_gemm_ex(8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, 9, None, 0, None) == li.LI_ERR_BAD_ENUM
+    need = lib.li_gemm_ex_workspace_bytes(8, 8, 8, li.LI_BF16X3)
+    assert need >= 2 * 2 * 8 * 8
+    assert lib.li_gemm_ex(8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, li.LI_BF16X3, FAKE + (1 << 20), need - 2, None) == li.LI_ERR_WORKSPACE
+    assert lib.li_round16(16, FAKE, FAKE + 64, FAKE + 128, li.LI_FP16, None) == li.LI_ERR_BAD_ENUM
+
+
+def test_tuning_table(li):
+    for k in (li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_GEMM_LP):
+        n = li.li_tune_num_candidates(k)
+        assert n >= 3
+        for i in range(n):
+            c = li.li_tune_candidate(k, i)
+            assert c["bm"] % 32 == 0 and c["bn"] % 32 == 0 and c["bk"] % 8 == 0
+            if k == li.LI_KERNEL_SYRK_F32:
+                assert c["bm"] == c["bn"]
+    assert li.li_tune_bucket(2048, 2048, 2048) == 12
+    assert li.li_tune_bucket(1, 1, 1) == 1
+    b = li.li_tune_bucket(300, 200, 100)
+    assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == -1
+    li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 2)
+    assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == 2
+    li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, -1)
+    assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == -1
+    with pytest.raises(li.LiError):
+        li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 999)
+    with pytest.raises(li.LiError):
+        li.li_tune_force(7, 0)

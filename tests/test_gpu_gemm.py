@@ -1,0 +1,206 @@
+"""GPU parity of the FP32 GEMM and the two-GEMM chain against the FP64
+oracle (calls go through the C ABI via the ctypes binding)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2312_13170_amd import synth
+from gpu_util import TOL_FP32, dev, empty, host, normwise, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def li():
+    from paper_2312_13170_amd import li as mod
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mod.li_init()
+    return mod
+
+
+def run_gemm(li, A, B, C0, alpha, beta, precision="fp32"):
+    M, K = A.shape
+    N = B.shape[1]
+    dA, dB = dev(A), dev(B)
+    dC = dev(C0) if C0 is not None else empty((M, N), fill=float("nan"))
+    if precision == "fp32":
+        li.li_gemm(M, N, K, alpha, dA, dB, beta, dC)
+    else:
+        ws = empty((li.li_gemm_ex_workspace_bytes(M, N, K, precision) // 4 + 1,))
+        li.li_gemm_ex(M, N, K, alpha, dA, dB, beta, dC, precision, ws)
+    return host(dC)
+
+
+def test_identity_gives_scaled_sum(li, orc):
+    say("gemm identity 100x77")
+    n, N = 100, 77
+    A = np.eye(n, dtype=np.float32)
+    B = synth.uniform_pm1(31, "B", (n, N))
+    C0 = synth.uniform_pm1(31, "C", (n, N))
+    out = run_gemm(li, A, B, C0, 1.5, 1.2)
+    ref = orc.gemm(A, B, C0, alpha=1.5, beta=1.2)
+    # at most two roundings of alpha*b + beta*c (with or without a fused
+    # multiply-add): |err| <= 2u (|alpha b| + |beta c|), u = 2^-24
+    bound = 2 * 2.0 ** -24 * (1.5 * np.abs(B.astype(np.float64)) + 1.2 * np.abs(C0.astype(np.float64)))
+    assert np.all(np.abs(out - ref) <= bound * 1.0001 + 1e-45)
+
+
+def test_integer_inputs_bitwise(li, orc):
+    say("gemm integer 300x200x1000")
+    M, N, K = 300, 200, 1000
+    A = synth.integer_matrix(32, "A", (M, K), -8, 8)
+    B = synth.integer_matrix(32, "B", (K, N), -8, 8)
+    C0 = synth.integer_matrix(32, "C", (M, N), -8, 8)
+    out = run_gemm(li, A, B, C0, 2.0, 1.0)
+    ref = orc.gemm(A, B, C0, alpha=2.0, beta=1.0)
+    assert np.array_equal(out.astype(np.float64), ref)
+
+
+def test_rank_one(li, orc):
+    say("gemm rank-1 70x90x129")
+    M, N, K = 70, 90, 129
+    u = 2.0 ** (np.arange(M) % 7 - 3)
+    w = 2.0 ** -(np.arange(N) % 5)
+    A = np.repeat(u[:, None], K, axis=1).astype(np.float32)
+    B = np.repeat(w[None, :], K, axis=0).astype(np.float32)
+    out = run_gemm(li, A, B, None, 1.0, 0.0)
+    assert np.array_equal(out.astype(np.float64), orc.gemm(A, B))
+
+
+SMALL = [1, 2, 3, 5, 7, 8, 13, 16, 31, 33, 63, 64, 65, 70]
+
+
+def test_brute_force_small_shapes(li, orc):
+    for M in SMALL[::2]:
+        for N in SMALL[1::2]:
+            for K in SMALL[::3]:
+                say("gemm small", M, N, K)
+                A = synth.uniform_pm1(33, "A%d_%d_%d" % (M, N, K), (M, K))
+                B = synth.uniform_pm1(33, "B%d_%d_%d" % (M, N, K), (K, N))
+                C0 = synth.uniform_pm1(33, "C%d_%d_%d" % (M, N, K), (M, N))
+                out = run_gemm(li, A, B, C0, 1.5, 1.2)
+                ref = orc.gemm(A, B, C0, alpha=1.5, beta=1.2)
+                assert normwise(out, ref) < 1e-6, (M, N, K)
+
+
+def test_config0(li, orc):
+    say("gemm 256^3 alpha 1.5 beta 1.2")
+    c = synth.config(0)
+    out = run_gemm(li, c["A"], c["B"], c["C"], c["alpha"], c["beta"])
+    ref = orc.gemm(c["A"], c["B"], c["C"], alpha=c["alpha"], beta=c["beta"])
+    assert normwise(out, ref) < TOL_FP32
+
+
+@pytest.mark.parametrize("shape", [(515, 387, 301), (1000, 1030, 260), (129, 1100, 67)])
+def test_every_tile_shape(li, orc, shape):
+    M, N, K = shape
+    A = synth.uniform_pm1(34, "A", (M, K))
+    B = synth.uniform_pm1(34, "B", (K, N))
+    C0 = synth.uniform_pm1(34, "C", (M, N))
+    ref = orc.gemm(A, B, C0, alpha=1.5, beta=1.2)
+    try:
+        for cfg in range(li.li_tune_num_candidates(li.LI_KERNEL_GEMM_F32)):
+            say("gemm", shape, "candidate", cfg)
+            li.li_tune_force(li.LI_KERNEL_GEMM_F32, cfg)
+            out = run_gemm(li, A, B, C0, 1.5, 1.2)
+            assert normwise(out, ref) < TOL_FP32, cfg
+    finally:
+        li.li_tune_force(li.LI_KERNEL_GEMM_F32, -1)
+
+
+def test_unaligned_operands(li, orc):
+    # K, N not multiples of 4 and operands at odd float offsets: scalar loads.
+    say("gemm unaligned")
+    M, N, K = 45, 51, 37
+    A = synth.uniform_pm1(35, "A", (M, K))
+    B = synth.uniform_pm1(35, "B", (K, N))
+    C0 = synth.uniform_pm1(35, "C", (M, N))
+    bufA = empty((M * K + 1,))
+    bufB = empty((K * N + 3,))
+    bufA[1:].copy_(dev(A).reshape(-1))
+    bufB[3:].copy_(dev(B).reshape(-1))
+    dC = dev(C0)
+    li.li_gemm(M, N, K, 1.5, bufA.data_ptr() + 4, bufB.data_ptr() + 12, 1.2, dC)
+    out = host(dC)
+    assert normwise(out, orc.gemm(A, B, C0, alpha=1.5, beta=1.2)) < 1e-6
+
+
+def test_degenerate_scalars(li, orc):
+    M, N, K = 40, 50, 60
+    C0 = synth.uniform_pm1(36, "C", (M, N))
+    nanA = np.full((M, K), np.nan, dtype=np.float32)
+    nanB = np.full((K, N), np.nan, dtype=np.float32)
+    say("gemm alpha=0 with NaN A, B")
+    out = run_gemm(li, nanA, nanB, C0, 0.0, 1.2)
+    assert np.array_equal(out, (np.float32(1.2) * C0).astype(np.float32)) or \
+        np.max(np.abs(out - 1.2 * C0.astype(np.float64))) < 1e-6
+    say("gemm beta=0 with NaN C")
+    A = synth.uniform_pm1(36, "A", (M, K))
+    B = synth.uniform_pm1(36, "B", (K, N))
+    out = run_gemm(li, A, B, None, 1.5, 0.0)
+    assert np.all(np.isfinite(out))
+    assert normwise(out, orc.gemm(A, B, alpha=1.5)) < 1e-6
+    say("gemm K=0")
+    dC = dev(C0)
+    li.li_gemm(M, N, 0, 1.5, None, None, 1.2, dC)
+    assert np.max(np.abs(host(dC) - 1.2 * C0.astype(np.float64))) < 1e-6
+    say("gemm M=0 and N=0 leave C untouched")
+    dC = dev(C0)
+    li.li_gemm(0, N, K, 1.5, None, None, 1.2, dC)
+    li.li_gemm(M, 0, K, 1.5, None, None, 1.2, dC)
+    assert np.array_equal(host(dC), C0)
+
+
+def test_repeatable_bitwise(li):
+    say("gemm repeatability 777x555x333")
+    M, N, K = 777, 555, 333
+    A = synth.uniform_pm1(37, "A", (M, K))
+    B = synth.uniform_pm1(37, "B", (K, N))
+    C0 = synth.uniform_pm1(37, "C", (M, N))
+    a = run_gemm(li, A, B, C0, 1.5, 1.2)
+    b = run_gemm(li, A, B, C0, 1.5, 1.2)
+    assert np.array_equal(a, b)
+
+
+def run_mm2(li, c):
+    NI, NJ, NK, NL = c["NI"], c["NJ"], c["NK"], c["NL"]
+    dA, dB, dC, dD = dev(c["A"]), dev(c["B"]), dev(c["C"]), dev(c["D"])
+    tmp = empty((NI, NJ), fill=float("nan"))
+    li.li_mm2(NI, NJ, NK, NL, c["alpha"], c["beta"], dA, dB, tmp, dC, dD)
+    return host(tmp), host(dD)
+
+
+def test_mm2_small_ragged(li, orc):
+    for dims in [(33, 65, 17, 70), (130, 7, 260, 129), (1, 1, 1, 1)]:
+        say("mm2", dims)
+        c = synth.mm2_inputs(*dims, seed=38)
+        tmp, D = run_mm2(li, c)
+        rt, rD = orc.mm2(c["A"], c["B"], c["C"], c["D"], alpha=c["alpha"], beta=c["beta"])
+        assert normwise(tmp, rt) < 1e-6
+        assert normwise(D, rD) < TOL_FP32
+
+
+def test_mm2_identity(li, orc):
+    say("mm2 identity chain")
+    n, NL = 96, 130
+    c = synth.mm2_inputs(n, n, n, NL, seed=39)
+    c["A"] = np.eye(n, dtype=np.float32)
+    c["B"] = np.eye(n, dtype=np.float32)
+    tmp, D = run_mm2(li, c)
+    assert np.array_equal(tmp, 1.5 * np.eye(n, dtype=np.float32))
+    ref = 1.5 * c["C"].astype(np.float64) + 1.2 * c["D"].astype(np.float64)
+    bound = 3 * 2.0 ** -24 * (1.5 * np.abs(c["C"].astype(np.float64)) + 1.2 * np.abs(c["D"].astype(np.float64)))
+    assert np.all(np.abs(D - ref) <= bound * 1.0001 + 1e-45)
+
+
+def test_mm2_config1_sampled_rows(li, orc):
+    say("mm2 2048^4 (sampled rows)")
+    c = synth.config(1)
+    tmp, D = run_mm2(li, c)
+    rows = np.array([0, 1, 127, 128, 1023, 1500, 2046, 2047])
+    rt, rD = orc.mm2(c["A"], c["B"], c["C"], c["D"], alpha=c["alpha"], beta=c["beta"], rows=rows)
+    assert normwise(tmp[rows], rt) < TOL_FP32
+    assert normwise(D[rows], rD) < TOL_FP32
+    # a property that holds at any size: repeat runs are bitwise identical
+    tmp2, D2 = run_mm2(li, c)
+    assert np.array_equal(D, D2) and np.array_equal(tmp, tmp2)

@@ -1,0 +1,135 @@
+"""GPU parity of covariance and correlation (FP64 column statistics,
+centring / normalisation and the symmetric contraction) against the FP64
+oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2312_13170_amd import synth
+from gpu_util import TOL_FP32, dev, empty, host, normwise, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def li():
+    from paper_2312_13170_amd import li as mod
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mod.li_init()
+    return mod
+
+
+def run_stats(li, X, corr, eps=0.1, inplace=False):
+    N, M = X.shape
+    dX = dev(X)
+    dY = dX if inplace else empty((N, M), fill=float("nan"))
+    mean = empty((M,), torch.float64, fill=float("nan"))
+    std = empty((M,), torch.float64, fill=float("nan")) if corr else None
+    out = empty((M, M), fill=float("nan"))
+    ws = empty((li.li_stats_workspace_bytes(M, N) // 8 + 1,), torch.float64)
+    if corr:
+        li.li_correlation(M, N, eps, dX, dY, mean, std, out, ws)
+    else:
+        li.li_covariance(M, N, dX, dY, mean, out, ws)
+    return host(dY), host(mean), (host(std) if corr else None), host(out)
+
+
+def test_constant_columns(li, orc):
+    say("stats constant columns")
+    N, M = 200, 70
+    X = synth.stats_inputs(N, M, seed=41)["data"]
+    consts = {0: 3.25, 17: -1024.5, 69: 1000.0}
+    for j, c in consts.items():
+        X[:, j] = c
+    Y, mean, _, cov = run_stats(li, X, corr=False)
+    Yc, meanc, std, corr = run_stats(li, X, corr=True)
+    for j, c in consts.items():
+        assert mean[j] == c and meanc[j] == c
+        assert np.all(Y[:, j] == 0.0) and np.all(Yc[:, j] == 0.0)
+        assert np.all(cov[j, :] == 0.0) and np.all(cov[:, j] == 0.0)
+        assert std[j] == 1.0
+        assert corr[j, j] == 1.0
+        assert np.all(np.delete(corr[j, :], j) == 0.0)
+
+
+@pytest.mark.parametrize("n", [98, 99])
+def test_identity_data(li, orc, n):
+    say("stats identity data", n)
+    X = np.eye(n, dtype=np.float32)
+    _, mean, _, cov = run_stats(li, X, corr=False)
+    _, _, std, corr = run_stats(li, X, corr=True)
+    J = np.ones((n, n))
+    assert np.allclose(mean, 1.0 / n, rtol=1e-14)
+    assert normwise(cov, (np.eye(n) - J / n) / (n - 1)) < 1e-6
+    off = ~np.eye(n, dtype=bool)
+    if n == 98:
+        assert np.allclose(std, math.sqrt(n - 1) / n, rtol=1e-13)
+        assert np.allclose(corr[off], -1.0 / (n - 1), rtol=1e-5)
+    else:
+        assert np.all(std == 1.0)
+        assert np.allclose(corr[off], -1.0 / n ** 2, rtol=1e-5)
+    assert np.all(np.diag(corr) == 1.0)
+
+
+@pytest.mark.parametrize("N,M", [(2, 1), (37, 5), (300, 129), (1000, 250), (513, 600)])
+@pytest.mark.parametrize("inplace", [False, True])
+def test_against_oracle(li, orc, N, M, inplace):
+    say("stats", N, M, "inplace" if inplace else "")
+    X = synth.stats_inputs(N, M, seed=42)["data"]
+    if M > 3:
+        X[:, 3] = 0.05 * X[:, 3]  # a column that may fall under the clamp
+    Y, mean, _, cov = run_stats(li, X, corr=False, inplace=inplace)
+    rY, rmean, rcov = orc.covariance(X)
+    assert np.allclose(mean, rmean, rtol=1e-12, atol=1e-12)
+    assert normwise(Y, rY) < 1e-7
+    assert normwise(cov, rcov) < TOL_FP32
+    assert np.array_equal(cov, cov.T)
+    Yc, meanc, std, corr = run_stats(li, X, corr=True, inplace=inplace)
+    rYc, rmeanc, rstd, rcorr = orc.correlation(X)
+    assert np.allclose(std, rstd, rtol=1e-12, atol=1e-14)
+    assert normwise(Yc, rYc) < 1e-7
+    assert normwise(corr, rcorr) < TOL_FP32
+    assert np.array_equal(corr, corr.T) and np.all(np.diag(corr) == 1.0)
+
+
+def test_every_tile_shape(li, orc):
+    N, M = 333, 300
+    X = synth.stats_inputs(N, M, seed=43)["data"]
+    _, _, rcov = orc.covariance(X, want_y=False)
+    try:
+        for cfg in range(li.li_tune_num_candidates(li.LI_KERNEL_SYRK_F32)):
+            say("covariance candidate", cfg)
+            li.li_tune_force(li.LI_KERNEL_SYRK_F32, cfg)
+            _, _, _, cov = run_stats(li, X, corr=False)
+            assert normwise(cov, rcov) < TOL_FP32, cfg
+            assert np.array_equal(cov, cov.T)
+    finally:
+        li.li_tune_force(li.LI_KERNEL_SYRK_F32, -1)
+
+
+def test_config2_full_size_sampled(li, orc):
+    say("stats 4096 x 2048 (sampled entries)")
+    inp = synth.config(2)
+    X = inp["data"]
+    N, M = X.shape
+    pa = synth.integer_matrix(44, "pa", (200,), 0, M - 1).astype(np.int64)
+    pb = synth.integer_matrix(44, "pb", (200,), 0, M - 1).astype(np.int64)
+    pa = np.concatenate([pa, [0, M - 1, 5]])
+    pb = np.concatenate([pb, [M - 1, M - 1, 5]])
+    for corr in (False, True):
+        Y, mean, std, out = run_stats(li, X, corr=corr)
+        rY, rmean, rstd = orc.centred_data(X, correlation=corr)
+        assert np.allclose(mean, rmean, rtol=1e-12, atol=1e-12)
+        assert normwise(Y, rY) < 1e-7
+        if corr:
+            assert np.allclose(std, rstd, rtol=1e-12)
+            ref = orc.correlation_entries(X, pa, pb)
+        else:
+            ref = orc.covariance_entries(X, pa, pb)
+        got = out[pa, pb]
+        # entry error against the largest magnitude of the result (normwise)
+        scale = np.max(np.abs(np.diag(out))) if not corr else 1.0
+        assert np.max(np.abs(got - ref)) / scale < TOL_FP32
+        assert np.array_equal(out, out.T)

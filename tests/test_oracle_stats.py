@@ -116,3 +116,18 @@ def test_mean_std_helpers(orc):
     s = orc.col_std(X, m)
     assert np.allclose(m, X.astype(np.float64).mean(axis=0), rtol=1e-14, atol=1e-16)
     assert np.allclose(s, X.astype(np.float64).std(axis=0), rtol=1e-13)
+
+
+def test_centred_data_matches_full(orc):
+    inp = synth.stats_inputs(70, 25, seed=16)
+    X = inp["data"]
+    X[:, 2] = -7.5
+    Y, mean, cov = orc.covariance(X)
+    Yc, mc, sc = orc.centred_data(X, correlation=False)
+    assert np.array_equal(Y, Yc) and np.array_equal(mean, mc) and sc is None
+    Y2, m2, s2, _ = orc.correlation(X)
+    Yr, mr, sr = orc.centred_data(X, correlation=True)
+    assert np.array_equal(Y2, Yr) and np.array_equal(s2, sr)
+    # normalised columns have unit sum of squares unless clamped
+    ss = (Yr ** 2).sum(axis=0)
+    assert np.allclose(np.delete(ss, 2), 1.0, rtol=1e-12) and ss[2] == 0.0
