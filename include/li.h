@@ -199,6 +199,12 @@ int32_t li_tune_get(int32_t kernel, int32_t bucket);
 /* Force one candidate for every call of a family (-1 clears): used by the
  * search to time each candidate through the ordinary entry points. */
 li_status li_tune_force(int32_t kernel, int32_t index);
+/* Persist / restore the table as text, one "kernel bucket index" line per
+ * set entry ('#' starts a comment).  Loading replaces every entry it names
+ * and rejects the whole file (changing nothing) if any line is malformed or
+ * out of range (LI_ERR_NOT_FOUND if the file cannot be opened). */
+li_status li_tune_save(const char *path);
+li_status li_tune_load(const char *path);
 
 #ifdef __cplusplus
 }

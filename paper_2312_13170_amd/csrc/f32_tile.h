@@ -52,11 +52,15 @@ __device__ __forceinline__ void grouped_tile(int t, int tiles_m, int tiles_n, in
     tn = in / gm;
 }
 
+// Global-load modes: scalar loads, 16-byte vector loads, or either chosen at
+// run time by a flag (one code path for problems of both kinds).
+enum { kLoadScalar = 0, kLoadVec4 = 1, kLoadDynamic = 2 };
+
 // Copies a TR x TC tile of a row-major matrix (rows x cols, leading
 // dimension ld) starting at (r0, c0) to LDS (leading dimension LDL), four
 // consecutive columns per chunk, zero-filling everything outside the matrix.
-// VEC4 requires cols % 4 == 0, ld % 4 == 0 and a 16-byte aligned base.
-template <int TR, int TC, int NT, bool VEC4>
+// Vector loads require cols % 4 == 0, ld % 4 == 0 and a 16-byte aligned base.
+template <int TR, int TC, int NT, int MODE>
 struct TileLoader {
     static constexpr int CPR = TC / 4;
     static constexpr int NCH = TR * CPR;
@@ -66,14 +70,16 @@ struct TileLoader {
     f32x4 v[PER];
 
     __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
-                                         int64_t cols, int64_t r0, int64_t c0, int tid)
+                                         int64_t cols, int64_t r0, int64_t c0, int tid,
+                                         bool dyn_vec4)
     {
+        const bool vec4 = MODE == kLoadVec4 || (MODE == kLoadDynamic && dyn_vec4);
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int c = tid + i * NT;
             const int r = c / CPR, cc = (c % CPR) * 4;
             const int64_t gr = r0 + r, gc = c0 + cc;
-            if (VEC4) {
+            if (vec4) {
                 if (gr < rows && gc < cols)
                     v[i] = *reinterpret_cast<const f32x4 *>(p + gr * ld + gc);
                 else
@@ -104,7 +110,8 @@ struct TileLoader {
 // A_KMAJOR: A element (m, k) is at A[k*lda + m] (the transposed operand of
 // the symmetric contraction); otherwise at A[m*lda + k].  B element (k, n)
 // is always at B[k*ldb + n].
-template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, bool VEC4>
+// LOAD: kLoadScalar, kLoadVec4 or kLoadDynamic (flag passed to mainloop).
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD>
 struct F32Tile {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
@@ -120,8 +127,8 @@ struct F32Tile {
     static constexpr int B_STAGE = BK * B_LD;
     static constexpr int LDS_FLOATS = 2 * (A_STAGE + B_STAGE);
 
-    using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, VEC4>;
-    using BLoader = TileLoader<BK, BN, NT, VEC4>;
+    using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
+    using BLoader = TileLoader<BK, BN, NT, LOAD>;
 
     __device__ __forceinline__ static void zero(f32x16 (&acc)[TM][TN])
     {
@@ -135,12 +142,12 @@ struct F32Tile {
 
     __device__ __forceinline__ static void load_a(ALoader &la, const float *A, int64_t lda,
                                                   int64_t M, int64_t kend, int64_t m0, int64_t k0,
-                                                  int tid)
+                                                  int tid, bool v4)
     {
         if (A_KMAJOR)
-            la.load(A, lda, kend, M, k0, m0, tid);
+            la.load(A, lda, kend, M, k0, m0, tid, v4);
         else
-            la.load(A, lda, M, kend, m0, k0, tid);
+            la.load(A, lda, M, kend, m0, k0, tid, v4);
     }
 
     // Inner loop over one LDS K-tile.
@@ -184,10 +191,12 @@ struct F32Tile {
     // Full reduction over k in [kbeg, kend) for the block tile at (m0, n0).
     // Must be reached by every thread of the work-group (it contains
     // barriers); the trip count depends only on uniform values.
+    // With LOAD == kLoadDynamic, v4 selects vector loads at run time.
     __device__ __forceinline__ static void mainloop(float *lds, const float *A, int64_t lda,
                                                     const float *B, int64_t ldb, int64_t M,
                                                     int64_t N, int64_t kbeg, int64_t kend,
-                                                    int64_t m0, int64_t n0, f32x16 (&acc)[TM][TN])
+                                                    int64_t m0, int64_t n0, f32x16 (&acc)[TM][TN],
+                                                    bool v4 = true)
     {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
@@ -198,8 +207,8 @@ struct F32Tile {
         if (nk <= 0) return;
         ALoader la;
         BLoader lb;
-        load_a(la, A, lda, M, kend, m0, kbeg, tid);
-        lb.load(B, ldb, kend, N, kbeg, n0, tid);
+        load_a(la, A, lda, M, kend, m0, kbeg, tid, v4);
+        lb.load(B, ldb, kend, N, kbeg, n0, tid, v4);
         la.template store<A_LD>(As, tid);
         lb.template store<B_LD>(Bs, tid);
         __syncthreads();
@@ -208,8 +217,8 @@ struct F32Tile {
             const bool more = kt + 1 < nk;
             if (more) {
                 const int64_t k1 = kbeg + (kt + 1) * BK;
-                load_a(la, A, lda, M, kend, m0, k1, tid);
-                lb.load(B, ldb, kend, N, k1, n0, tid);
+                load_a(la, A, lda, M, kend, m0, k1, tid, v4);
+                lb.load(B, ldb, kend, N, k1, n0, tid, v4);
             }
             compute(As + cur * A_STAGE, Bs + cur * B_STAGE, acc, wm0, wn0, lane);
             if (more) {
@@ -256,6 +265,50 @@ struct F32Tile {
                 }
             }
     }
+
+    // Symmetric result S (M x M): the tile at (m0, n0) with n0 >= m0 writes
+    // each value to S[r][c] and S[c][r] from the same register, so S is
+    // bitwise symmetric; on a diagonal tile only r <= c is written.
+    // mode 0: value * scale; mode 1: value, diagonal forced to 1.0.
+    __device__ __forceinline__ static void epilogue_syrk(const f32x16 (&acc)[TM][TN], float *S,
+                                                         int64_t M, int64_t m0, int64_t n0,
+                                                         int mode, float scale)
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+        const bool diag_tile = m0 == n0;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int64_t col = n0 + acc_col(wn0, j, lane);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = m0 + acc_row(wm0, i, v, lane);
+                    if (row >= M || col >= M) continue;
+                    if (diag_tile && row > col) continue;
+                    float val = acc[i][j][v];
+                    if (mode == 0)
+                        val *= scale;
+                    else if (row == col)
+                        val = 1.0f;
+                    S[row * M + col] = val;
+                    if (row != col) S[col * M + row] = val;
+                }
+            }
+    }
 };
+
+// Upper-triangle tile t of a tiles x tiles grid (row-major over tm <= tn).
+__device__ __forceinline__ void upper_tile(int t, int tiles, int &tm, int &tn)
+{
+    int r = 0;
+    while (t >= tiles - r) {
+        t -= tiles - r;
+        ++r;
+    }
+    tm = r;
+    tn = r + t;
+}
 
 }  // namespace li

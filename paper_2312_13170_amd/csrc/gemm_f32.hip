@@ -36,17 +36,6 @@ __global__ __launch_bounds__(T::NT) void gemm_f32_kernel(const float *__restrict
 // tile column >= tile row are computed; each value is written to S[r][c]
 // and S[c][r] from the same register, so S is bitwise symmetric.
 // mode 0: S *= scale; mode 1: diagonal set to 1.0.
-__device__ __forceinline__ void upper_tile(int t, int T, int &tm, int &tn)
-{
-    int r = 0;
-    while (t >= T - r) {
-        t -= T - r;
-        ++r;
-    }
-    tm = r;
-    tn = r + t;
-}
-
 template <class T>
 __global__ __launch_bounds__(T::NT) void syrk_f32_kernel(const float *__restrict__ Y, int64_t M,
                                                          int64_t N, float *__restrict__ S,
@@ -63,29 +52,7 @@ __global__ __launch_bounds__(T::NT) void syrk_f32_kernel(const float *__restrict
     T::zero(acc);
     // A = Y^T (element (m, k) at Y[k*M + m]), B = Y; reduction over samples.
     T::mainloop(lds, Y, M, Y, M, M, M, 0, N, m0, n0, acc);
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm0 = (wave / T::WN) * (T::BM / T::WM), wn0 = (wave % T::WN) * (T::BN / T::WN);
-    const bool diag_tile = tm == tn;
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < T::TN; ++j) {
-            const int64_t col = n0 + T::acc_col(wn0, j, lane);
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int64_t row = m0 + T::acc_row(wm0, i, v, lane);
-                if (row >= M || col >= M) continue;
-                if (diag_tile && row > col) continue;
-                float val = acc[i][j][v];
-                if (mode == 0)
-                    val *= scale;
-                else if (row == col)
-                    val = 1.0f;
-                S[row * M + col] = val;
-                if (row != col) S[col * M + row] = val;
-            }
-        }
+    T::epilogue_syrk(acc, S, M, m0, n0, mode, scale);
 }
 
 template <class T>
@@ -125,9 +92,9 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
     switch (cfg) {
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK)                                                       \
     case IDX:                                                                                      \
-        return v4 ? run_gemm<F32Tile<BM, BN, BK, WM, WN, false, true>>(M, N, K, alpha, A, lda, B, \
+        return v4 ? run_gemm<F32Tile<BM, BN, BK, WM, WN, false, kLoadVec4>>(M, N, K, alpha, A, lda, B, \
                                                                         ldb, beta, C, ldc, s)      \
-                  : run_gemm<F32Tile<BM, BN, BK, WM, WN, false, false>>(M, N, K, alpha, A, lda, B, \
+                  : run_gemm<F32Tile<BM, BN, BK, WM, WN, false, kLoadScalar>>(M, N, K, alpha, A, lda, B, \
                                                                          ldb, beta, C, ldc, s);
         LI_GEMM_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
@@ -144,8 +111,8 @@ int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int
     switch (cfg) {
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK)                                                       \
     case IDX:                                                                                      \
-        return v4 ? run_syrk<F32Tile<BM, BN, BK, WM, WN, true, true>>(M, N, Y, S, mode, scale, s)  \
-                  : run_syrk<F32Tile<BM, BN, BK, WM, WN, true, false>>(M, N, Y, S, mode, scale, s);
+        return v4 ? run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadVec4>>(M, N, Y, S, mode, scale, s)  \
+                  : run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadScalar>>(M, N, Y, S, mode, scale, s);
         LI_SYRK_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
     default:

@@ -13,6 +13,8 @@ namespace li {
 // ---------------------------------------------------------------- errors
 // Records a message for li_last_error() and returns `s`.
 li_status fail(li_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+// LI_ERR_HIP with the HIP error's name (api.cpp).
+li_status hip_fail(int err, const char *what);
 
 // ---------------------------------------------------------------- validation
 // (validate.cpp: plain C++, no HIP headers, so it is testable without a GPU)
@@ -57,7 +59,15 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
 int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode,
                     float scale, void *stream);
 
-// Column statistics (FP64) and centring / normalisation.
+// Column statistics (FP64) and centring / normalisation.  The rows of a
+// column are cut into nsplit chunks of rows_per_split rows (stats.hip).
+constexpr int kStatThreads = 256;
+constexpr int64_t kMinRowsPerSplit = 32;
+struct StatsPlan {
+    int64_t nsplit, rows_per_split;
+    int col_blocks;
+};
+StatsPlan stats_plan(int64_t M, int64_t N);
 size_t stats_workspace_bytes(int64_t M, int64_t N);
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
                  int correlation, double eps, void *ws, void *stream);

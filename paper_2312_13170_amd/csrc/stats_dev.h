@@ -1,0 +1,79 @@
+// Device functions of the FP64 column statistics, shared by the
+// single-problem kernels (stats.hip) and the grouped kernels (grouped.hip) so
+// that both produce bitwise the same means, deviations and centred data.
+//
+// A column is cut into chunks of `rows_per_split` rows.  Per chunk, the
+// shifted sums s1 = sum(x - x0), s2 = sum((x - x0)^2) with x0 the chunk's
+// first value give the chunk mean x0 + s1/n and centred sum of squares
+// max(s2 - s1^2/n, 0).  Chunks are merged in increasing order with the
+// pairwise update of Chan, Golub and LeVeque (1979).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace li {
+
+__device__ __forceinline__ void chunk_moments(const float *col, int64_t ld, int64_t r0, int64_t r1,
+                                              double &mean, double &m2)
+{
+    const double x0 = (double)col[r0 * ld];
+    double s1 = 0.0, s2 = 0.0;
+    int64_t r = r0;
+    for (; r + 4 <= r1; r += 4) {
+        const double d0 = (double)col[(r + 0) * ld] - x0;
+        const double d1 = (double)col[(r + 1) * ld] - x0;
+        const double d2 = (double)col[(r + 2) * ld] - x0;
+        const double d3 = (double)col[(r + 3) * ld] - x0;
+        s1 += d0;
+        s2 += d0 * d0;
+        s1 += d1;
+        s2 += d1 * d1;
+        s1 += d2;
+        s2 += d2 * d2;
+        s1 += d3;
+        s2 += d3 * d3;
+    }
+    for (; r < r1; ++r) {
+        const double d = (double)col[r * ld] - x0;
+        s1 += d;
+        s2 += d * d;
+    }
+    const double n = (double)(r1 - r0);
+    double q = s2 - s1 * (s1 / n);
+    if (q < 0.0) q = 0.0;
+    mean = x0 + s1 / n;
+    m2 = q;
+}
+
+// (na, ma, m2a) <- merge with (nb, mb, m2b)
+__device__ __forceinline__ void chan_merge(double &na, double &ma, double &m2a, double nb, double mb,
+                                           double m2b)
+{
+    const double n = na + nb;
+    const double d = mb - ma;
+    ma = ma + d * (nb / n);
+    m2a = m2a + m2b + d * d * (na * nb / n);
+    na = n;
+}
+
+// Clamped population standard deviation and the normalisation factor.
+__device__ __forceinline__ void finish_std(double m2, int64_t N, double eps, double &sd,
+                                           double &factor)
+{
+    double var = m2 / (double)N;
+    if (var < 0.0) var = 0.0;
+    sd = sqrt(var);
+    if (sd <= eps) sd = 1.0;
+    factor = 1.0 / (sqrt((double)N) * sd);
+}
+
+// One centred (or normalised) value, rounded once to FP32.
+__device__ __forceinline__ float centre_value(float x, double mean, double factor, bool scale)
+{
+    double v = (double)x - mean;
+    if (scale) v *= factor;
+    return (float)v;
+}
+
+}  // namespace li

@@ -4,6 +4,8 @@
 // "forced" candidate overrides everything for one family: the search
 // (autotune.py) forces each candidate in turn and times the ordinary entry
 // points with HIP events, then writes the winners back with li_tune_set.
+#include <stdio.h>
+
 #include <atomic>
 
 #include "li_internal.h"
@@ -157,6 +159,56 @@ li_status li_tune_force(int32_t kernel, int32_t index)
     if (index < -1 || index >= n)
         return li::fail(LI_ERR_NOT_FOUND, "candidate %d out of range [-1, %d)", index, n);
     li::g_forced[kernel].store(index + 1);
+    return LI_OK;
+}
+
+li_status li_tune_save(const char *path)
+{
+    if (!path) return li::fail(LI_ERR_NULL_POINTER, "path is NULL");
+    FILE *f = fopen(path, "w");
+    if (!f) return li::fail(LI_ERR_NOT_FOUND, "cannot write %s", path);
+    fprintf(f, "# li tuning table (gfx950): kernel bucket candidate\n");
+    for (int k = 0; k < li::kFamilies; ++k)
+        for (int b = 0; b < li::kBuckets; ++b) {
+            const int v = li::g_table[k][b].load() - 1;
+            if (v >= 0) fprintf(f, "%d %d %d\n", k, b, v);
+        }
+    const bool ok = fclose(f) == 0;
+    return ok ? LI_OK : li::fail(LI_ERR_NOT_FOUND, "writing %s failed", path);
+}
+
+li_status li_tune_load(const char *path)
+{
+    if (!path) return li::fail(LI_ERR_NULL_POINTER, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return li::fail(LI_ERR_NOT_FOUND, "cannot open %s", path);
+    struct Entry {
+        int k, b, v;
+    };
+    Entry entries[li::kFamilies * li::kBuckets];
+    int n = 0, line_no = 0;
+    char line[256];
+    li_status st = LI_OK;
+    while (st == LI_OK && fgets(line, sizeof(line), f)) {
+        ++line_no;
+        char *p = line;
+        while (*p == ' ' || *p == '\t') ++p;
+        if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0) continue;
+        int k, b, v, cnt;
+        if (sscanf(p, "%d %d %d %n", &k, &b, &v, &cnt) != 3 || (p[cnt] != 0 && p[cnt] != '#')) {
+            st = li::fail(LI_ERR_INVALID_SIZE, "%s:%d: expected 'kernel bucket candidate'", path, line_no);
+            break;
+        }
+        int nc;
+        if (!li::family(k, &nc) || b < 0 || b >= li::kBuckets || v < 0 || v >= nc) {
+            st = li::fail(LI_ERR_INVALID_SIZE, "%s:%d: entry out of range", path, line_no);
+            break;
+        }
+        if (n < li::kFamilies * li::kBuckets) entries[n++] = {k, b, v};
+    }
+    fclose(f);
+    if (st != LI_OK) return st;
+    for (int i = 0; i < n; ++i) li::g_table[entries[i].k][entries[i].b].store(entries[i].v + 1);
     return LI_OK;
 }
 

@@ -79,6 +79,8 @@ _SIGS = {
     "li_tune_set": ([_i32, _i32, _i32], _i32),
     "li_tune_get": ([_i32, _i32], _i32),
     "li_tune_force": ([_i32, _i32], _i32),
+    "li_tune_save": ([ctypes.c_char_p], _i32),
+    "li_tune_load": ([ctypes.c_char_p], _i32),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -263,3 +265,18 @@ def li_tune_get(kernel, bucket) -> int:
 
 def li_tune_force(kernel, index) -> None:
     _check(_lib.li_tune_force(kernel, index))
+
+
+def li_tune_save(path) -> None:
+    _check(_lib.li_tune_save(os.fsencode(path)))
+
+
+def li_tune_load(path) -> None:
+    _check(_lib.li_tune_load(os.fsencode(path)))
+
+
+# Tuning table written by autotune.py on an MI355X; LI_TUNE_TABLE overrides
+# the path ("" disables loading).
+TUNE_TABLE = os.environ.get("LI_TUNE_TABLE", os.path.join(_PKG, "tune_gfx950.txt"))
+if TUNE_TABLE and os.path.exists(TUNE_TABLE):
+    li_tune_load(TUNE_TABLE)

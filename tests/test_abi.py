@@ -122,3 +122,58 @@ def test_tuning_table(li):
         li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 999)
     with pytest.raises(li.LiError):
         li.li_tune_force(7, 0)
+
+
+def test_group_plan_validation(li):
+    P = li.make_problem
+    G, COV = li.LI_PROBLEM_GEMM, li.LI_PROBLEM_COVARIANCE
+    mb = 4 * 64 * 64
+    ok_a = P(G, 64, 64, 64, 1.0, 0.0, FAKE, FAKE + mb, FAKE + 2 * mb)
+    # second problem writes into the first one's C
+    clash = P(G, 64, 64, 64, 1.0, 0.0, FAKE + 3 * mb, FAKE + 4 * mb, FAKE + 2 * mb + 64)
+    with pytest.raises(li.LiError) as e:
+        li.li_group_plan_create([ok_a, clash])
+    assert e.value.status == li.LI_ERR_OVERLAP
+    # an output overlapping another problem's input
+    clash2 = P(G, 64, 64, 64, 1.0, 0.0, FAKE + 3 * mb, FAKE + 4 * mb, FAKE + 8)
+    with pytest.raises(li.LiError) as e:
+        li.li_group_plan_create([ok_a, clash2])
+    assert e.value.status == li.LI_ERR_OVERLAP
+    with pytest.raises(li.LiError) as e:
+        li.li_group_plan_create([P(7, 4, 4, 4, 1.0, 0.0, FAKE, FAKE, FAKE)])
+    assert e.value.status == li.LI_ERR_BAD_ENUM
+    with pytest.raises(li.LiError) as e:
+        li.li_group_plan_create([P(G, 4, 4, 4, 1.0, 0.0, None, FAKE, FAKE + 4096)])
+    assert e.value.status == li.LI_ERR_NULL_POINTER
+    with pytest.raises(li.LiError) as e:
+        li.li_group_plan_create([P(COV, 8, 1, 0, 1.0, 0.0, FAKE, None, FAKE + 4096, FAKE + 8192, FAKE + 16384)])
+    assert e.value.status == li.LI_ERR_INVALID_SIZE
+
+
+def test_tune_table_save_load(li, tmp_path):
+    k = li.LI_KERNEL_SYRK_F32
+    b1, b2 = 20, 21
+    old1, old2 = li.li_tune_get(k, b1), li.li_tune_get(k, b2)
+    try:
+        li.li_tune_set(k, b1, 1)
+        li.li_tune_set(k, b2, 2)
+        path = tmp_path / "t.txt"
+        li.li_tune_save(str(path))
+        text = path.read_text()
+        assert "%d %d 1" % (k, b1) in text and "%d %d 2" % (k, b2) in text
+        li.li_tune_set(k, b1, -1)
+        li.li_tune_set(k, b2, -1)
+        li.li_tune_load(str(path))
+        assert li.li_tune_get(k, b1) == 1 and li.li_tune_get(k, b2) == 2
+        # a malformed file changes nothing
+        bad = tmp_path / "bad.txt"
+        bad.write_text("%d %d 0\n%d 999 0\n" % (k, b1, k))
+        with pytest.raises(li.LiError):
+            li.li_tune_load(str(bad))
+        assert li.li_tune_get(k, b1) == 1
+        with pytest.raises(li.LiError) as e:
+            li.li_tune_load(str(tmp_path / "missing.txt"))
+        assert e.value.status == li.LI_ERR_NOT_FOUND
+    finally:
+        li.li_tune_set(k, b1, old1)
+        li.li_tune_set(k, b2, old2)
