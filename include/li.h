@@ -185,6 +185,7 @@ typedef struct li_tile_config {
     int32_t bm, bn, bk;     /* block tile and K-tile                    */
     int32_t waves_m, waves_n;
     int32_t split_k;        /* reduction split (1 = none)               */
+    int32_t prefetch;       /* K-tiles in flight from HBM (1 or 2)      */
 } li_tile_config;
 
 int32_t li_tune_num_candidates(int32_t kernel);

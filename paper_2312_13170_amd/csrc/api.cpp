@@ -248,7 +248,8 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
         return s;
     const int cfg = li::tune_pick(LI_KERNEL_SYRK_F32, M, M, N);
     const float scale = corr ? 1.0f : (float)(1.0 / (double)(N - 1));
-    return launched(li::launch_syrk_f32(cfg, M, N, data_out, out, corr ? 1 : 0, scale, stream),
+    float *split_ws = (float *)((char *)ws + li::stats_part_bytes(M, N));
+    return launched(li::launch_syrk_f32(cfg, M, N, data_out, out, corr ? 1 : 0, scale, split_ws, stream),
                     "symmetric contraction launch");
 }
 

@@ -60,6 +60,11 @@ enum { kLoadScalar = 0, kLoadVec4 = 1, kLoadDynamic = 2 };
 // dimension ld) starting at (r0, c0) to LDS (leading dimension LDL), four
 // consecutive columns per chunk, zero-filling everything outside the matrix.
 // Vector loads require cols % 4 == 0, ld % 4 == 0 and a 16-byte aligned base.
+// The loads are unconditional: a lane whose chunk lies outside the matrix
+// reads the matrix's first element(s) instead (always valid: a load happens
+// only when rows, cols >= 1, and cols >= 4 with vector loads) and keeps
+// zeros.  Without branches around loads the compiler can issue them all at
+// once and count them exactly in its waits.
 template <int TR, int TC, int NT, int MODE>
 struct TileLoader {
     static constexpr int CPR = TC / 4;
@@ -79,16 +84,19 @@ struct TileLoader {
             const int c = tid + i * NT;
             const int r = c / CPR, cc = (c % CPR) * 4;
             const int64_t gr = r0 + r, gc = c0 + cc;
+            const bool rok = gr < rows;
             if (vec4) {
-                if (gr < rows && gc < cols)
-                    v[i] = *reinterpret_cast<const f32x4 *>(p + gr * ld + gc);
-                else
-                    v[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const bool ok = rok && gc < cols;
+                const f32x4 x = *reinterpret_cast<const f32x4 *>(p + (ok ? gr * ld + gc : 0));
+                v[i] = ok ? x : f32x4{0.f, 0.f, 0.f, 0.f};
             } else {
-                const bool rok = gr < rows;
-                const float *q = p + gr * ld + gc;
+                const int64_t base = gr * ld + gc;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[i][e] = (rok && gc + e < cols) ? q[e] : 0.f;
+                for (int e = 0; e < 4; ++e) {
+                    const bool ok = rok && gc + e < cols;
+                    const float x = p[ok ? base + e : 0];
+                    v[i][e] = ok ? x : 0.f;
+                }
             }
         }
     }
@@ -111,8 +119,10 @@ struct TileLoader {
 // the symmetric contraction); otherwise at A[m*lda + k].  B element (k, n)
 // is always at B[k*ldb + n].
 // LOAD: kLoadScalar, kLoadVec4 or kLoadDynamic (flag passed to mainloop).
-template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD>
+// PF: K-tiles in flight from HBM (1: the next tile; 2: the next two).
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1>
 struct F32Tile {
+    static_assert(PF == 1 || PF == 2, "prefetch depth is 1 or 2");
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
@@ -211,6 +221,42 @@ struct F32Tile {
         lb.load(B, ldb, kend, N, kbeg, n0, tid, v4);
         la.template store<A_LD>(As, tid);
         lb.template store<B_LD>(Bs, tid);
+        if (PF == 2) {
+            // Two K-tiles in flight: the registers of one set are being
+            // filled from HBM while the other set (loaded one step earlier)
+            // is written to the idle LDS buffer.  The loop is unrolled by two
+            // so each register set is named statically.  Loads past the end
+            // read the zero-filled out-of-range tile (no branch, so the
+            // compiler's wait counts stay exact).
+            ALoader la1;
+            BLoader lb1;
+            load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4);
+            lb1.load(B, ldb, kend, N, kbeg + BK, n0, tid, v4);
+            __syncthreads();
+            int64_t kt = 0;
+            for (; kt + 2 <= nk; kt += 2) {
+                const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
+                load_a(la, A, lda, M, kend, m0, k2, tid, v4);
+                lb.load(B, ldb, kend, N, k2, n0, tid, v4);
+                compute(As, Bs, acc, wm0, wn0, lane);
+                la1.template store<A_LD>(As + A_STAGE, tid);
+                lb1.template store<B_LD>(Bs + B_STAGE, tid);
+                __syncthreads();
+                load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
+                lb1.load(B, ldb, kend, N, k3, n0, tid, v4);
+                compute(As + A_STAGE, Bs + B_STAGE, acc, wm0, wn0, lane);
+                if (kt + 2 < nk) {
+                    la.template store<A_LD>(As, tid);
+                    lb.template store<B_LD>(Bs, tid);
+                }
+                __syncthreads();
+            }
+            if (kt < nk) {
+                compute(As, Bs, acc, wm0, wn0, lane);
+                __syncthreads();
+            }
+            return;
+        }
         __syncthreads();
         for (int64_t kt = 0; kt < nk; ++kt) {
             const int cur = (int)(kt & 1);

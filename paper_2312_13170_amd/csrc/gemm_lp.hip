@@ -422,7 +422,7 @@ int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alp
         if (e != hipSuccess) return (int)e;
     }
     switch (cfg) {
-#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK)                                                      \
+#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                    \
     case IDX:                                                                                     \
         if (prec == 3) return run_lp<LpTile<BM, BN, (BK > 32 ? 32 : BK), WM, WN, 3, false>>(L, M, N, alpha, beta, C, s); \
         if (prec == 2) return run_lp<LpTile<BM, BN, BK, WM, WN, 1, true>>(L, M, N, alpha, beta, C, s); \

@@ -469,7 +469,7 @@ li_status li_group_plan_launch_loop(li_group_plan *plan, li_stream stream)
             err = li::launch_stats(q.M, q.N, q.A, q.data_out, q.mean, nullptr, 0, 0.0, plan->loop_ws, stream);
             if (!err)
                 err = li::launch_syrk_f32(plan->cfg[i], q.M, q.N, q.data_out, q.C, 0,
-                                          (float)(1.0 / (double)(q.N - 1)), stream);
+                                          (float)(1.0 / (double)(q.N - 1)), nullptr, stream);
         }
         if (err) return li::hip_fail(err, "per-instance launch");
     }

@@ -36,7 +36,7 @@ int device_cu_count();       // compute units of the current device
 
 // ---------------------------------------------------------------- tuning
 struct TileCfg {
-    int bm, bn, bk, wm, wn, split_k;
+    int bm, bn, bk, wm, wn, split_k, prefetch;
 };
 int tune_num(int kernel);
 const TileCfg &tune_cfg(int kernel, int idx);
@@ -55,9 +55,11 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
 
 // Symmetric contraction S = Y^T Y (Y: N x M row-major), upper block tiles
 // computed and mirrored.  mode 0: S *= scale (covariance); mode 1: diagonal
-// forced to 1.0 (correlation).
+// forced to 1.0 (correlation).  Candidates with split_k > 1 need split_ws of
+// syrk_split_bytes(M) bytes (the largest any candidate uses).
+size_t syrk_split_bytes(int64_t M);
 int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode,
-                    float scale, void *stream);
+                    float scale, float *split_ws, void *stream);
 
 // Column statistics (FP64) and centring / normalisation.  The rows of a
 // column are cut into nsplit chunks of rows_per_split rows (stats.hip).
@@ -68,7 +70,8 @@ struct StatsPlan {
     int col_blocks;
 };
 StatsPlan stats_plan(int64_t M, int64_t N);
-size_t stats_workspace_bytes(int64_t M, int64_t N);
+size_t stats_part_bytes(int64_t M, int64_t N);      // statistics part of the workspace
+size_t stats_workspace_bytes(int64_t M, int64_t N);  // statistics + contraction split
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
                  int correlation, double eps, void *ws, void *stream);
 

@@ -119,11 +119,18 @@ __global__ __launch_bounds__(256) void centre_kernel_v4(const float *X, float *Y
 
 }  // namespace
 
+// Layout: [chunk partials nsplit x 2 x M doubles][factor M doubles]
+//         [split-K partials of the contraction, syrk_split_bytes(M)]
+size_t stats_part_bytes(int64_t M, int64_t N)
+{
+    StatsPlan p = stats_plan(M, N);
+    return (size_t)(p.nsplit * 2 * M + M) * sizeof(double);
+}
+
 size_t stats_workspace_bytes(int64_t M, int64_t N)
 {
     if (M <= 0 || N <= 0) return 0;
-    StatsPlan p = stats_plan(M, N);
-    return (size_t)(p.nsplit * 2 * M + M) * sizeof(double);
+    return stats_part_bytes(M, N) + syrk_split_bytes(M);
 }
 
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,

@@ -1,32 +1,39 @@
 // Compiled tile shapes of each kernel family.  The host tuning table
 // (tune.cpp) indexes these lists; the kernel files instantiate exactly these
-// shapes.  Keep the two in step: the static_asserts in the kernel files check
-// every entry against its template instantiation.
-#pragma once
+// shapes.  The grouped kernels (grouped.hip) check at plan time that the
+// candidates they share with the single-problem kernels have the same shape.
 
-// {bm, bn, bk, waves_m, waves_n, split_k}
-#define LI_GEMM_F32_CANDIDATES(X)       \
-    X(0, 128, 128, 32, 2, 2, 1)         \
-    X(1, 128, 128, 16, 2, 2, 1)         \
-    X(2, 64, 64, 32, 2, 2, 1)           \
-    X(3, 128, 64, 32, 2, 2, 1)          \
-    X(4, 64, 128, 32, 2, 2, 1)          \
-    X(5, 128, 128, 32, 2, 4, 1)         \
-    X(6, 256, 128, 16, 2, 2, 1)         \
-    X(7, 64, 64, 16, 1, 1, 1)
+// {index, bm, bn, bk, waves_m, waves_n, split_k, prefetch depth}
+#define LI_GEMM_F32_CANDIDATES(X)            \
+    X(0, 128, 128, 32, 2, 2, 1, 1)           \
+    X(1, 128, 128, 16, 2, 2, 1, 1)           \
+    X(2, 64, 64, 32, 2, 2, 1, 1)             \
+    X(3, 128, 64, 32, 2, 2, 1, 1)            \
+    X(4, 64, 128, 32, 2, 2, 1, 1)            \
+    X(5, 128, 128, 32, 2, 4, 1, 1)           \
+    X(6, 128, 128, 32, 2, 4, 1, 2)           \
+    X(7, 128, 128, 32, 4, 4, 1, 1)           \
+    X(8, 128, 128, 64, 2, 4, 1, 1)           \
+    X(9, 128, 128, 32, 4, 4, 1, 2)           \
+    X(10, 64, 64, 32, 2, 2, 1, 2)
 
 // square block tiles only (upper-triangle enumeration)
-#define LI_SYRK_F32_CANDIDATES(X)       \
-    X(0, 128, 128, 32, 2, 2, 1)         \
-    X(1, 128, 128, 16, 2, 2, 1)         \
-    X(2, 64, 64, 32, 2, 2, 1)           \
-    X(3, 128, 128, 32, 2, 4, 1)         \
-    X(4, 64, 64, 16, 1, 1, 1)
+#define LI_SYRK_F32_CANDIDATES(X)            \
+    X(0, 128, 128, 32, 2, 2, 1, 1)           \
+    X(1, 128, 128, 16, 2, 2, 1, 1)           \
+    X(2, 64, 64, 32, 2, 2, 1, 1)             \
+    X(3, 128, 128, 32, 2, 4, 1, 1)           \
+    X(4, 64, 64, 32, 2, 2, 1, 2)             \
+    X(5, 128, 128, 32, 2, 4, 1, 2)           \
+    X(6, 128, 128, 32, 2, 4, 2, 1)           \
+    X(7, 128, 128, 32, 2, 4, 4, 1)           \
+    X(8, 128, 128, 32, 2, 2, 4, 1)           \
+    X(9, 128, 128, 32, 2, 4, 7, 1)
 
-// bf16 / fp16 matrix-core GEMM on pre-rounded operands
-#define LI_GEMM_LP_CANDIDATES(X)        \
-    X(0, 256, 256, 32, 2, 4, 1)         \
-    X(1, 128, 128, 64, 2, 2, 1)         \
-    X(2, 256, 128, 32, 2, 2, 1)         \
-    X(3, 128, 256, 32, 2, 2, 1)         \
-    X(4, 64, 64, 64, 2, 2, 1)
+// bf16 / fp16 matrix-core GEMM on pre-rounded operands (prefetch unused)
+#define LI_GEMM_LP_CANDIDATES(X)             \
+    X(0, 256, 256, 32, 2, 4, 1, 1)           \
+    X(1, 128, 128, 64, 2, 2, 1, 1)           \
+    X(2, 256, 128, 32, 2, 2, 1, 1)           \
+    X(3, 128, 256, 32, 2, 2, 1, 1)           \
+    X(4, 64, 64, 64, 2, 2, 1, 1)

@@ -14,7 +14,7 @@
 namespace li {
 namespace {
 
-#define LI_ENTRY(IDX, BM, BN, BK, WM, WN, SK) {BM, BN, BK, WM, WN, SK},
+#define LI_ENTRY(IDX, BM, BN, BK, WM, WN, SK, PF) {BM, BN, BK, WM, WN, SK, PF},
 const TileCfg kGemmF32[] = {LI_GEMM_F32_CANDIDATES(LI_ENTRY)};
 const TileCfg kSyrkF32[] = {LI_SYRK_F32_CANDIDATES(LI_ENTRY)};
 const TileCfg kGemmLp[] = {LI_GEMM_LP_CANDIDATES(LI_ENTRY)};
@@ -117,6 +117,7 @@ li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out)
     out->waves_m = f[index].wm;
     out->waves_n = f[index].wn;
     out->split_k = f[index].split_k;
+    out->prefetch = f[index].prefetch;
     return LI_OK;
 }
 

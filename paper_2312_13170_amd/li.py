@@ -47,7 +47,7 @@ _p = ctypes.c_void_p
 
 class li_tile_config(ctypes.Structure):
     _fields_ = [("bm", _i32), ("bn", _i32), ("bk", _i32), ("waves_m", _i32),
-                ("waves_n", _i32), ("split_k", _i32)]
+                ("waves_n", _i32), ("split_k", _i32), ("prefetch", _i32)]
 
 
 class li_problem(ctypes.Structure):

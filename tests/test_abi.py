@@ -113,13 +113,16 @@ def test_tuning_table(li):
     assert li.li_tune_bucket(2048, 2048, 2048) == 12
     assert li.li_tune_bucket(1, 1, 1) == 1
     b = li.li_tune_bucket(300, 200, 100)
-    assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == -1
-    li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 2)
-    assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == 2
-    li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, -1)
-    assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == -1
-    with pytest.raises(li.LiError):
-        li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 999)
+    old = li.li_tune_get(li.LI_KERNEL_GEMM_F32, b)
+    try:
+        li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 3)
+        assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == 3
+        li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, -1)
+        assert li.li_tune_get(li.LI_KERNEL_GEMM_F32, b) == -1
+        with pytest.raises(li.LiError):
+            li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, 999)
+    finally:
+        li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, old)
     with pytest.raises(li.LiError):
         li.li_tune_force(7, 0)
 
