@@ -285,6 +285,13 @@ struct F32Tile {
         return wn0 + 32 * tn + (lane & 31);
     }
 
+    // alpha*acc + beta*c with one explicit fused multiply-add, so every
+    // kernel that forms C rounds it identically.
+    __device__ __forceinline__ static float combine(float alpha, float a, float beta, float c)
+    {
+        return __builtin_fmaf(beta, c, alpha * a);
+    }
+
     // C = alpha*acc + beta*C over the in-range part of the tile.
     __device__ __forceinline__ static void epilogue_gemm(const f32x16 (&acc)[TM][TN], float *C,
                                                          int64_t ldc, int64_t M, int64_t N,
@@ -304,10 +311,55 @@ struct F32Tile {
                     const int64_t row = m0 + acc_row(wm0, tm, v, lane);
                     if (row < M && col < N) {
                         float *c = C + row * ldc + col;
-                        float r = alpha * acc[tm][tn][v];
-                        if (beta != 0.f) r += beta * *c;
-                        *c = r;
+                        *c = beta != 0.f ? combine(alpha, acc[tm][tn][v], beta, *c) : alpha * acc[tm][tn][v];
                     }
+                }
+            }
+    }
+
+    // The tile's current C values, read before the reduction starts so their
+    // latency hides behind it (out-of-range entries read C[0] and are unused).
+    __device__ __forceinline__ static void load_c(float (&cv)[TM][TN][16], const float *C,
+                                                  int64_t ldc, int64_t M, int64_t N, int64_t m0,
+                                                  int64_t n0)
+    {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                const int64_t col = n0 + acc_col(wn0, tn, lane);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = m0 + acc_row(wm0, tm, v, lane);
+                    const bool ok = row < M && col < N;
+                    cv[tm][tn][v] = C[ok ? row * ldc + col : 0];
+                }
+            }
+    }
+
+    // C = alpha*acc + beta*cv (cv from load_c) over the in-range part.
+    __device__ __forceinline__ static void epilogue_gemm_loaded(const f32x16 (&acc)[TM][TN],
+                                                                const float (&cv)[TM][TN][16],
+                                                                float *C, int64_t ldc, int64_t M,
+                                                                int64_t N, int64_t m0, int64_t n0,
+                                                                float alpha, float beta)
+    {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                const int64_t col = n0 + acc_col(wn0, tn, lane);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int64_t row = m0 + acc_row(wm0, tm, v, lane);
+                    if (row < M && col < N)
+                        C[row * ldc + col] = combine(alpha, acc[tm][tn][v], beta, cv[tm][tn][v]);
                 }
             }
     }
