@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--rows-only", action="store_true",
                    help="measure only the rows named by --rows (no headline line)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped",
+    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped,forms,paper1024",
                    help="comma list of extra rows to measure")
     return p.parse_args()
 
@@ -282,10 +282,48 @@ def measure_rows(args, torch, li, synth, timer):
         del A, B, C, ws
 
     if "grouped" in want:
-        try:
-            rows["grouped"] = measure_grouped(torch, li, synth, timer)
-        except Exception as exc:  # grouped plans may be absent from a build
-            rows["grouped"] = {"error": str(exc)}
+        rows["grouped"] = measure_grouped(torch, li, synth, timer)
+
+    if "forms" in want:
+        # the paper's polybench size (1024): the GEMM in each form the device
+        # passes produce, then the production matrix-core kernel
+        n = 1024
+        c = synth.gemm_inputs(n, n, n, seed=1)
+        A, B, C0 = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+        C = C0.clone()
+        f = gemm_flops(n, n, n)
+        res = {}
+        for form in ("naive", "reduced", "internalized"):
+            ms = timer.time(lambda: li.li_gemm_form(form, n, n, n, 1.5, A, B, 1.2, C), 5, 1)
+            res[form] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1)}
+        ms = timer.time(lambda: li.li_gemm(n, n, n, 1.5, A, B, 1.2, C), reps, 1)
+        res["matrix_core"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1)}
+        base = res["naive"]["ms"]
+        for k in res:
+            res[k]["speedup_vs_naive"] = round(base / res[k]["ms"], 2)
+        rows["gemm_1024_forms"] = res
+        del A, B, C0, C
+
+    if "paper1024" in want:
+        # the four kernels at the paper's problem size 1024
+        n = 1024
+        m = synth.mm2_inputs(n, n, n, n, seed=2)
+        dA, dB, dC, dD = (torch.from_numpy(m[k]).cuda() for k in ("A", "B", "C", "D"))
+        tmp = torch.empty((n, n), device="cuda")
+        ms = timer.time(lambda: li.li_mm2(n, n, n, n, 1.5, 1.2, dA, dB, tmp, dC, dD), reps, 1)
+        rows["mm2_1024"] = {"ms": round(ms, 4), "GFLOP/s": round(2 * gemm_flops(n, n, n) / ms / 1e6, 1)}
+        s = synth.stats_inputs(n, n, seed=3)
+        X = torch.from_numpy(s["data"]).cuda()
+        Y = torch.empty_like(X)
+        mean = torch.empty(n, dtype=torch.float64, device="cuda")
+        std = torch.empty(n, dtype=torch.float64, device="cuda")
+        out = torch.empty((n, n), device="cuda")
+        ws = torch.empty(li.li_stats_workspace_bytes(n, n) // 8 + 1, dtype=torch.float64, device="cuda")
+        f = syrk_flops(n, n)
+        ms = timer.time(lambda: li.li_covariance(n, n, X, Y, mean, out, ws), reps, 1)
+        rows["cov_1024"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1)}
+        ms = timer.time(lambda: li.li_correlation(n, n, 0.1, X, Y, mean, std, out, ws), reps, 1)
+        rows["corr_1024"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1)}
     return rows
 
 

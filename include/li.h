@@ -95,6 +95,23 @@ li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *
                      const float *B, float beta, float *C, li_precision p,
                      void *workspace, size_t workspace_bytes, li_stream stream);
 
+/* The GEMM of li_gemm in the forms the paper's device optimisations turn it
+ * into, for measuring each transformation on this GPU (scalar FP32 fused
+ * multiply-adds, k summed in increasing order, no matrix cores):
+ *   LI_FORM_NAIVE         one work-item per C element; C[i][j] is scaled by
+ *                         beta and then updated in memory at every k (the
+ *                         matrix-multiply listing of Sec. VI-C with the
+ *                         polybench beta scaling);
+ *   LI_FORM_REDUCED       the same with the sum in a register, C read and
+ *                         written once (after detect reduction, Sec. VI-B);
+ *   LI_FORM_INTERNALIZED  16 x 16 work-groups, k tiled by 16, A and B tiles
+ *                         staged in LDS between two barriers, the sum in a
+ *                         register (after loop internalization, Sec. VI-C).
+ * Same arguments and rules as li_gemm; M and N are limited to 1048560. */
+typedef enum { LI_FORM_NAIVE = 0, LI_FORM_REDUCED = 1, LI_FORM_INTERNALIZED = 2 } li_gemm_form_t;
+li_status li_gemm_form(int32_t form, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                       const float *B, float beta, float *C, li_stream stream);
+
 /* 2mm (polybench two-GEMM chain, Sec. VIII):
  *   tmp = alpha * A * B        A: NI x NK, B: NK x NJ, tmp: NI x NJ (written)
  *   D   = tmp * C + beta * D   C: NJ x NL, D: NI x NL (read and written)

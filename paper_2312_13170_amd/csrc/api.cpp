@@ -155,6 +155,21 @@ li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *
                     "gemm_lp launch");
 }
 
+li_status li_gemm_form(int32_t form, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                       const float *B, float beta, float *C, li_stream stream)
+{
+    uint64_t ab, bb, cb;
+    li_status s = validate_gemm(M, N, K, alpha, A, B, beta, C, &ab, &bb, &cb);
+    if (s) return s;
+    if (form != LI_FORM_NAIVE && form != LI_FORM_REDUCED && form != LI_FORM_INTERNALIZED)
+        return li::fail(LI_ERR_BAD_ENUM, "unknown GEMM form %d", form);
+    if (M > 1048560 || N > 1048560)
+        return li::fail(LI_ERR_INVALID_SIZE, "the work-item forms support M, N <= 1048560");
+    if ((s = li::ensure_device())) return s;
+    if (M == 0 || N == 0) return LI_OK;
+    return launched(li::launch_gemm_form(form, M, N, K, alpha, A, B, beta, C, stream), "gemm form launch");
+}
+
 li_status li_mm2(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, float alpha, float beta,
                  const float *A, const float *B, float *tmp, const float *C, float *D,
                  li_stream stream)

@@ -70,15 +70,30 @@ __global__ __launch_bounds__(kStatThreads) void grouped_stats(const GProb *__res
     const int64_t j = (int64_t)b.col0 + threadIdx.x;
     if (j >= M) return;
     const float *col = p.A + j;
-    const int64_t rps = p.rows_per_split;
-    double na = (double)(rps < N ? rps : N), ma, m2a;
-    chunk_moments(col, M, 0, rps < N ? rps : N, ma, m2a);
-    for (int64_t s = 1; s < p.nsplit; ++s) {
-        const int64_t r0 = s * rps;
-        const int64_t r1 = r0 + rps < N ? r0 + rps : N;
-        double mb, m2b;
-        chunk_moments(col, M, r0, r1, mb, m2b);
-        chan_merge(na, ma, m2a, (double)(r1 - r0), mb, m2b);
+    const int64_t rps = p.rows_per_split, nsplit = p.nsplit;
+    // same two-level merge order as the single-problem finaliser
+    const int64_t cpg = chunks_per_group(nsplit);
+    double n = 0.0, ma = 0.0, m2a = 0.0;
+    for (int g = 0; g < kMergeGroups; ++g) {
+        const int64_t s0 = g * cpg, s1 = s0 + cpg < nsplit ? s0 + cpg : nsplit;
+        if (s0 >= s1) continue;
+        int64_t r0, r1;
+        chunk_rows(s0, rps, N, r0, r1);
+        double gn = (double)(r1 - r0), gm, gq;
+        chunk_moments(col, M, r0, r1, gm, gq);
+        for (int64_t s = s0 + 1; s < s1; ++s) {
+            chunk_rows(s, rps, N, r0, r1);
+            double mb, m2b;
+            chunk_moments(col, M, r0, r1, mb, m2b);
+            chan_merge(gn, gm, gq, (double)(r1 - r0), mb, m2b);
+        }
+        if (g == 0) {
+            n = gn;
+            ma = gm;
+            m2a = gq;
+        } else {
+            chan_merge(n, ma, m2a, gn, gm, gq);
+        }
     }
     p.mean[j] = ma;
     float *ycol = p.Y + j;

@@ -75,6 +75,10 @@ size_t stats_workspace_bytes(int64_t M, int64_t N);  // statistics + contraction
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
                  int correlation, double eps, void *ws, void *stream);
 
+// Scalar work-item forms of the GEMM (gemm_forms.hip).
+int launch_gemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                     const float *B, float beta, float *C, void *stream);
+
 // Reduced-precision path
 size_t lp_workspace_bytes(int64_t M, int64_t N, int64_t K, int prec);
 int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alpha,

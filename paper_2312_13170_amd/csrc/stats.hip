@@ -56,26 +56,45 @@ __global__ __launch_bounds__(kStatThreads) void colstats_partial(const float *__
     part[(split * 2 + 1) * M + j] = m2;
 }
 
+// 32 columns per work-group; the kMergeGroups thread rows of a column merge
+// their groups of chunk partials in parallel, then one thread merges the
+// group results in order.
+constexpr int kFinCols = kStatThreads / kMergeGroups;
+
 __global__ __launch_bounds__(kStatThreads) void colstats_finalize(
     const double *__restrict__ part, int64_t nsplit, int64_t rows_per_split, int64_t N, int64_t M,
     int correlation, double eps, double *__restrict__ mean, double *__restrict__ stdv,
     double *__restrict__ factor)
 {
-    const int64_t j = (int64_t)blockIdx.x * kStatThreads + threadIdx.x;
-    if (j >= M) return;
-    double na = (double)(rows_per_split < N ? rows_per_split : N);
-    double ma = part[j];
-    double m2a = part[M + j];
-    for (int64_t s = 1; s < nsplit; ++s) {
-        const int64_t r0 = s * rows_per_split;
-        int64_t r1 = r0 + rows_per_split;
-        if (r1 > N) r1 = N;
-        chan_merge(na, ma, m2a, (double)(r1 - r0), part[(s * 2 + 0) * M + j], part[(s * 2 + 1) * M + j]);
+    __shared__ double gn[kMergeGroups][kFinCols], gm[kMergeGroups][kFinCols], gq[kMergeGroups][kFinCols];
+    const int c = threadIdx.x % kFinCols, g = threadIdx.x / kFinCols;
+    const int64_t j = (int64_t)blockIdx.x * kFinCols + c;
+    const int64_t cpg = chunks_per_group(nsplit);
+    const int64_t s0 = g * cpg, s1 = s0 + cpg < nsplit ? s0 + cpg : nsplit;
+    double na = 0.0, ma = 0.0, m2a = 0.0;
+    if (j < M && s0 < s1) {
+        int64_t r0, r1;
+        chunk_rows(s0, rows_per_split, N, r0, r1);
+        na = (double)(r1 - r0);
+        ma = part[(s0 * 2 + 0) * M + j];
+        m2a = part[(s0 * 2 + 1) * M + j];
+        for (int64_t s = s0 + 1; s < s1; ++s) {
+            chunk_rows(s, rows_per_split, N, r0, r1);
+            chan_merge(na, ma, m2a, (double)(r1 - r0), part[(s * 2 + 0) * M + j], part[(s * 2 + 1) * M + j]);
+        }
     }
-    mean[j] = ma;
+    gn[g][c] = na;
+    gm[g][c] = ma;
+    gq[g][c] = m2a;
+    __syncthreads();
+    if (g != 0 || j >= M) return;
+    double n = gn[0][c], m = gm[0][c], q = gq[0][c];
+    for (int h = 1; h < kMergeGroups; ++h)
+        if (gn[h][c] > 0.0) chan_merge(n, m, q, gn[h][c], gm[h][c], gq[h][c]);
+    mean[j] = m;
     if (correlation) {
         double sd, f;
-        finish_std(m2a, N, eps, sd, f);
+        finish_std(q, N, eps, sd, f);
         stdv[j] = sd;
         factor[j] = f;
     }
@@ -144,7 +163,8 @@ int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, d
                        0, s, X, N, M, p.rows_per_split, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(colstats_finalize, dim3(p.col_blocks), dim3(kStatThreads), 0, s, part,
+    hipLaunchKernelGGL(colstats_finalize, dim3((unsigned)((M + kFinCols - 1) / kFinCols)),
+                       dim3(kStatThreads), 0, s, part,
                        p.nsplit, p.rows_per_split, N, M, correlation, eps, mean, stdv, factor);
     e = hipGetLastError();
     if (e != hipSuccess) return (int)e;

@@ -57,6 +57,25 @@ __device__ __forceinline__ void chan_merge(double &na, double &ma, double &m2a, 
     na = n;
 }
 
+// Merge order of the chunk partials: the chunks are split into kMergeGroups
+// consecutive groups of chunks_per_group(nsplit) chunks; each group is merged
+// in chunk order, then the groups in group order.  The single-problem
+// finaliser merges the groups in parallel threads, the grouped kernel merges
+// everything in one thread; both follow this order exactly.
+constexpr int kMergeGroups = 8;
+
+__host__ __device__ __forceinline__ int64_t chunks_per_group(int64_t nsplit)
+{
+    return (nsplit + kMergeGroups - 1) / kMergeGroups;
+}
+
+// Rows [r0, r1) of chunk s of a column of N rows cut into rps-row chunks.
+__device__ __forceinline__ void chunk_rows(int64_t s, int64_t rps, int64_t N, int64_t &r0, int64_t &r1)
+{
+    r0 = s * rps;
+    r1 = r0 + rps < N ? r0 + rps : N;
+}
+
 // Clamped population standard deviation and the normalisation factor.
 __device__ __forceinline__ void finish_std(double m2, int64_t N, double eps, double &sd,
                                            double &factor)

@@ -63,6 +63,7 @@ _SIGS = {
     "li_gemm": ([_i64, _i64, _i64, _f32, _p, _p, _f32, _p, _p], _i32),
     "li_gemm_ex_workspace_bytes": ([_i64, _i64, _i64, _i32], _sz),
     "li_gemm_ex": ([_i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _p, _sz, _p], _i32),
+    "li_gemm_form": ([_i32, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _p], _i32),
     "li_mm2": ([_i64, _i64, _i64, _i64, _f32, _f32, _p, _p, _p, _p, _p, _p], _i32),
     "li_stats_workspace_bytes": ([_i64, _i64], _sz),
     "li_covariance": ([_i64, _i64, _p, _p, _p, _p, _p, _sz, _p], _i32),
@@ -147,6 +148,15 @@ def li_gemm_ex(M, N, K, alpha, A, B, beta, C, precision, workspace=None, workspa
         workspace_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _check(_lib.li_gemm_ex(M, N, K, alpha, _ptr(A), _ptr(B), beta, _ptr(C), p, _ptr(workspace),
                            workspace_bytes, _stream(stream)))
+
+
+LI_FORM_NAIVE, LI_FORM_REDUCED, LI_FORM_INTERNALIZED = 0, 1, 2
+FORMS = {"naive": LI_FORM_NAIVE, "reduced": LI_FORM_REDUCED, "internalized": LI_FORM_INTERNALIZED}
+
+
+def li_gemm_form(form, M, N, K, alpha, A, B, beta, C, stream=None) -> None:
+    _check(_lib.li_gemm_form(FORMS.get(form, form), M, N, K, alpha, _ptr(A), _ptr(B), beta, _ptr(C),
+                             _stream(stream)))
 
 
 def li_mm2(NI, NJ, NK, NL, alpha, beta, A, B, tmp, C, D, stream=None) -> None:

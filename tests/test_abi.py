@@ -92,6 +92,14 @@ def test_covariance_argument_rules(li):
                               FAKE + 8 * xb, ws, None) == li.LI_ERR_INVALID_SIZE
 
 
+def test_gemm_form_validation(li):
+    lib = li._lib
+    assert lib.li_gemm_form(5, 8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, None) == li.LI_ERR_BAD_ENUM
+    assert lib.li_gemm_form(0, -8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_gemm_form(1, 8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 16, None) == li.LI_ERR_OVERLAP
+    assert lib.li_gemm_form(2, 2000000, 8, 8, 1.0, FAKE, FAKE + (1 << 30), 0.0, FAKE + (1 << 31), None) == li.LI_ERR_INVALID_SIZE
+
+
 def test_precision_enum_and_workspace(li):
     lib = li._lib
     assert lib.li_gemm_ex(8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, 9, None, 0, None) == li.LI_ERR_BAD_ENUM
