@@ -119,10 +119,11 @@ struct TileLoader {
 // the symmetric contraction); otherwise at A[m*lda + k].  B element (k, n)
 // is always at B[k*ldb + n].
 // LOAD: kLoadScalar, kLoadVec4 or kLoadDynamic (flag passed to mainloop).
-// PF: K-tiles in flight from HBM (1: the next tile; 2: the next two).
+// PF: K-tiles in flight from HBM (1: the next tile; 2: the next two; 3: the
+// next two, with LDS operand reads pipelined across the barrier).
 template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1>
 struct F32Tile {
-    static_assert(PF == 1 || PF == 2, "prefetch depth is 1 or 2");
+    static_assert(PF >= 1 && PF <= 3, "prefetch mode is 1, 2 or 3");
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
@@ -198,6 +199,117 @@ struct F32Tile {
         }
     }
 
+    // Matrix-core operands of one 8-wide k step, read from LDS.
+    struct Frag {
+        float a[TM][4], b[TN][4];
+    };
+
+    __device__ __forceinline__ static void read_frag(const float *As, const float *Bs, int kk,
+                                                     int wm0, int wn0, int lane, Frag &f)
+    {
+        const int l32 = lane & 31, h4 = (lane >> 5) * 4;
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+            if (!A_KMAJOR) {
+                const f32x4 t =
+                    *reinterpret_cast<const f32x4 *>(As + (wm0 + 32 * tm + l32) * A_LD + kk + h4);
+                f.a[tm][0] = t[0];
+                f.a[tm][1] = t[1];
+                f.a[tm][2] = t[2];
+                f.a[tm][3] = t[3];
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) f.a[tm][s] = As[(kk + h4 + s) * A_LD + wm0 + 32 * tm + l32];
+            }
+        }
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) f.b[tn][s] = Bs[(kk + h4 + s) * B_LD + wn0 + 32 * tn + l32];
+    }
+
+    __device__ __forceinline__ static void mma(const Frag &f, f32x16 (&acc)[TM][TN])
+    {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < TN; ++tn)
+                    acc[tm][tn] =
+                        __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[tm][s], f.b[tn][s], acc[tm][tn], 0, 0, 0);
+    }
+
+    // All but the last k step of one LDS K-tile, each step's operands read
+    // one step ahead; on entry f holds step 0, on exit the last step.
+    __device__ __forceinline__ static void kloop(const float *As, const float *Bs, Frag &f,
+                                                 f32x16 (&acc)[TM][TN], int wm0, int wn0, int lane)
+    {
+#pragma unroll
+        for (int kk = 8; kk < BK; kk += 8) {
+            Frag g;
+            read_frag(As, Bs, kk, wm0, wn0, lane, g);
+            mma(f, acc);
+            f = g;
+        }
+    }
+
+    // PF == 3: two K-tiles in flight as with PF == 2, and the operand reads
+    // run one k step ahead of the matrix-core steps, also across the barrier:
+    // the last step of tile t is multiplied after the barrier, while the
+    // first operands of tile t + 1 are being read from LDS.
+    __device__ __forceinline__ static void mainloop_pipelined(
+        float *As, float *Bs, ALoader &la, BLoader &lb, const float *A, int64_t lda, const float *B,
+        int64_t ldb, int64_t M, int64_t N, int64_t kbeg, int64_t kend, int64_t m0, int64_t n0,
+        int64_t nk, f32x16 (&acc)[TM][TN], bool v4)
+    {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+        ALoader la1;
+        BLoader lb1;
+        load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4);
+        lb1.load(B, ldb, kend, N, kbeg + BK, n0, tid, v4);
+        __syncthreads();
+        Frag f;
+        read_frag(As, Bs, 0, wm0, wn0, lane, f);
+        int64_t kt = 0;
+        for (; kt + 2 <= nk; kt += 2) {
+            const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
+            load_a(la, A, lda, M, kend, m0, k2, tid, v4);
+            lb.load(B, ldb, kend, N, k2, n0, tid, v4);
+            kloop(As, Bs, f, acc, wm0, wn0, lane);
+            la1.template store<A_LD>(As + A_STAGE, tid);
+            lb1.template store<B_LD>(Bs + B_STAGE, tid);
+            __syncthreads();
+            {
+                Frag g;
+                read_frag(As + A_STAGE, Bs + B_STAGE, 0, wm0, wn0, lane, g);
+                mma(f, acc);
+                f = g;
+            }
+            load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
+            lb1.load(B, ldb, kend, N, k3, n0, tid, v4);
+            kloop(As + A_STAGE, Bs + B_STAGE, f, acc, wm0, wn0, lane);
+            if (kt + 2 < nk) {
+                la.template store<A_LD>(As, tid);
+                lb.template store<B_LD>(Bs, tid);
+                __syncthreads();
+                Frag g;
+                read_frag(As, Bs, 0, wm0, wn0, lane, g);
+                mma(f, acc);
+                f = g;
+            } else {
+                mma(f, acc);
+            }
+        }
+        if (kt < nk) {
+            kloop(As, Bs, f, acc, wm0, wn0, lane);
+            mma(f, acc);
+        }
+        __syncthreads();
+    }
+
     // Full reduction over k in [kbeg, kend) for the block tile at (m0, n0).
     // Must be reached by every thread of the work-group (it contains
     // barriers); the trip count depends only on uniform values.
@@ -221,6 +333,10 @@ struct F32Tile {
         lb.load(B, ldb, kend, N, kbeg, n0, tid, v4);
         la.template store<A_LD>(As, tid);
         lb.template store<B_LD>(Bs, tid);
+        if (PF == 3) {
+            mainloop_pipelined(As, Bs, la, lb, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc, v4);
+            return;
+        }
         if (PF == 2) {
             // Two K-tiles in flight: the registers of one set are being
             // filled from HBM while the other set (loaded one step earlier)

@@ -17,7 +17,11 @@
     X(9, 128, 128, 32, 4, 4, 1, 2)           \
     X(10, 64, 64, 32, 2, 2, 1, 2)            \
     X(11, 128, 128, 64, 4, 4, 1, 1)          \
-    X(12, 128, 128, 64, 2, 4, 1, 2)
+    X(12, 128, 128, 64, 2, 4, 1, 2)          \
+    X(13, 128, 128, 32, 2, 4, 1, 3)          \
+    X(14, 128, 128, 64, 2, 4, 1, 3)          \
+    X(15, 128, 128, 32, 4, 4, 1, 3)          \
+    X(16, 64, 64, 32, 2, 2, 1, 3)
 
 // square block tiles only (upper-triangle enumeration)
 #define LI_SYRK_F32_CANDIDATES(X)            \
@@ -33,7 +37,9 @@
     X(9, 128, 128, 32, 2, 4, 7, 1)           \
     X(10, 128, 128, 32, 4, 4, 7, 2)          \
     X(11, 128, 128, 64, 4, 4, 7, 1)          \
-    X(12, 128, 128, 64, 2, 4, 4, 1)
+    X(12, 128, 128, 64, 2, 4, 4, 1)          \
+    X(13, 128, 128, 32, 4, 4, 7, 3)          \
+    X(14, 128, 128, 32, 2, 4, 7, 3)
 
 // bf16 / fp16 matrix-core GEMM on pre-rounded operands (prefetch unused)
 #define LI_GEMM_LP_CANDIDATES(X)             \

@@ -36,6 +36,32 @@ def source_hash(files=KERNEL_SOURCES):
     return h.hexdigest()[:16]
 
 
+def hash_line(files):
+    """'Kernel sources hash: `H` (files: a, b)' for the given package files."""
+    return "Kernel sources hash: `%s` (files: %s)" % (source_hash(files), ", ".join(files))
+
+
+def parse_hash_line(text):
+    """(hash, files) from a summary's hash line, or (None, None)."""
+    import re
+    m = re.search(r"Kernel sources hash: `([0-9a-f]+)`(?: \(files: ([^)]*)\))?", text)
+    if not m:
+        return None, None
+    files = [f.strip() for f in m.group(2).split(",")] if m.group(2) else list(KERNEL_SOURCES)
+    return m.group(1), files
+
+
+def still_current(text):
+    """True when the kernel sources named in a summary are unchanged."""
+    h, files = parse_hash_line(text)
+    if h is None:
+        return False
+    try:
+        return h == source_hash(files)
+    except OSError:
+        return False
+
+
 def short(name, n=96):
     return name if len(name) <= n else name[: n - 3] + "..."
 
@@ -49,7 +75,7 @@ def trace(args):
     total = sum(sum(v) for v in agg.values())
     lines = ["# Kernel trace: %s" % args.title, "",
              "Command: `%s`" % args.cmd, "",
-             "Kernel sources hash: `%s`" % source_hash(), "",
+             hash_line(args.sources), "",
              "| kernel | calls | mean us | min us | max us | share of GPU time |",
              "|---|---|---|---|---|---|"]
     for n, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
@@ -82,7 +108,7 @@ def hbm(args):
              "Commands (one counter per run):", "",
              "    %s" % args.cmd.replace("COUNTER", "FETCH_SIZE"),
              "    %s" % args.cmd.replace("COUNTER", "WRITE_SIZE"), "",
-             "Kernel sources hash: `%s`" % source_hash(), "",
+             hash_line(args.sources), "",
              "Kernel: `%s` (%d dispatches)" % (short(kname, 140), len(fk)), "",
              "Calibration: the program copies %d bytes device-to-device once; the copy "
              "dispatch reads FETCH_SIZE = %.1f KiB and WRITE_SIZE = %.1f KiB, so the "
@@ -110,7 +136,7 @@ def pmc(args):
             agg.setdefault(c, []).append(v)
     mean = {c: sum(v) / len(v) for c, v in agg.items()}
     lines = ["# Counters: %s" % args.title, "", "Command: `%s`" % args.cmd, "",
-             "Kernel sources hash: `%s`" % source_hash(), "",
+             hash_line(args.sources), "",
              "Kernel: `%s`" % short(kname or "?", 140), "",
              "| counter | mean per dispatch |", "|---|---|"]
     for c, v in mean.items():
@@ -146,6 +172,8 @@ def main():
     for q in (t, h, c):
         q.add_argument("--cmd", required=True)
         q.add_argument("--title", default="")
+        q.add_argument("--sources", nargs="+", default=list(KERNEL_SOURCES),
+                       help="package files whose hash the summary records")
     a = p.parse_args()
     {"trace": trace, "hbm": hbm, "pmc": pmc}[a.mode](a)
 
