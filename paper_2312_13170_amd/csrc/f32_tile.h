@@ -120,10 +120,11 @@ struct TileLoader {
 // is always at B[k*ldb + n].
 // LOAD: kLoadScalar, kLoadVec4 or kLoadDynamic (flag passed to mainloop).
 // PF: K-tiles in flight from HBM (1: the next tile; 2: the next two; 3: the
-// next two, with LDS operand reads pipelined across the barrier).
+// next two, with LDS operand reads pipelined across the barrier; 4: direct
+// HBM-to-LDS loads into a three-stage ring, vector loads only).
 template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1>
 struct F32Tile {
-    static_assert(PF >= 1 && PF <= 3, "prefetch mode is 1, 2 or 3");
+    static_assert(PF >= 1 && PF <= 4, "prefetch mode is 1 to 4");
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
@@ -136,7 +137,10 @@ struct F32Tile {
     static constexpr int A_STAGE = (A_KMAJOR ? BK : BM) * A_LD;
     static constexpr int B_LD = BN + 8;
     static constexpr int B_STAGE = BK * B_LD;
-    static constexpr int LDS_FLOATS = 2 * (A_STAGE + B_STAGE);
+    // PF == 4 keeps three unpadded, XOR-swizzled stages filled by direct
+    // HBM-to-LDS loads (see mainloop_dma).
+    static constexpr int DMA_A = BM * BK, DMA_B = BK * BN;
+    static constexpr int LDS_FLOATS = PF == 4 ? 3 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
     using BLoader = TileLoader<BK, BN, NT, LOAD>;
@@ -310,6 +314,190 @@ struct F32Tile {
         __syncthreads();
     }
 
+    // ------------------------------------------------------------ PF == 4
+    // Direct HBM-to-LDS loads (global_load_lds_dwordx4): one instruction of a
+    // wave writes 64 x 16 bytes to one contiguous kilobyte of LDS, lane i at
+    // byte 16 i.  A lane may fetch any 16-byte chunk of the tile, so the
+    // chunk order inside an LDS row is permuted on the global side (XOR
+    // swizzle) and undone by the readers; rows stay unpadded:
+    //   row-major A [BM][BK]: physical chunk = logical ^ swz_rows(row)
+    //   k-major    [BK][W]:   physical chunk = logical ^ swz_k(k)
+    // (16 consecutive rows of one logical chunk, and the two k rows a
+    // fragment read touches, fall on distinct banks).  Lanes whose chunk
+    // lies outside the matrix read 16 zero bytes instead.  The ring has three
+    // stages: while tile t is multiplied, tiles t + 1 and t + 2 are in flight;
+    // one barrier per K-tile, preceded by an explicit wait for tile t + 1
+    // (the compiler's fence-carrying __syncthreads would wait for tile t + 2
+    // as well).
+    static constexpr int NW = WM * WN;
+
+    __device__ __forceinline__ static int swz_rows(int row)
+    {
+        return BK == 32 ? ((row ^ (row >> 3)) & 7) : (row & 15);
+    }
+    __device__ __forceinline__ static int swz_k(int k) { return ((k >> 2) & 1) << 3; }
+
+    __device__ __forceinline__ static const float *zero16()
+    {
+        static __device__ const float z[4] __attribute__((aligned(16))) = {0.f, 0.f, 0.f, 0.f};
+        return z;
+    }
+    static_assert(PF != 4 || BK == 32 || BK == 64, "direct LDS loads use K-tiles of 32 or 64");
+
+    __device__ __forceinline__ static void lds_dma(const float *src, float *dst)
+    {
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    }
+
+    // Row-major operand tile: TR rows of BK floats from (r0, k0).
+    template <int TR>
+    __device__ __forceinline__ static void dma_rows(float *stage, const float *P, int64_t ld,
+                                                    int64_t rows, int64_t kend, int64_t r0,
+                                                    int64_t k0, int wave, int lane)
+    {
+        constexpr int CH = BK / 4, RPI = 64 / CH, INS = TR / RPI;
+        static_assert(INS % NW == 0, "row tile must split evenly among waves");
+#pragma unroll
+        for (int q = 0; q < INS / NW; ++q) {
+            const int ins = wave * (INS / NW) + q;
+            const int row = ins * RPI + lane / CH;
+            const int logical = (lane % CH) ^ swz_rows(row);
+            const int64_t gr = r0 + row, gc = k0 + 4 * logical;
+            lds_dma(gr < rows && gc < kend ? P + gr * ld + gc : zero16(), stage + ins * 256);
+        }
+    }
+
+    // k-major operand tile: BK rows (k) of W floats from (k0, x0).
+    template <int W>
+    __device__ __forceinline__ static void dma_kmajor(float *stage, const float *P, int64_t ld,
+                                                      int64_t kend, int64_t cols, int64_t k0,
+                                                      int64_t x0, int wave, int lane)
+    {
+        constexpr int CH = W / 4, RPI = 64 / CH, INS = BK / RPI;
+        static_assert(CH >= 16 && 64 % CH == 0, "k-major tiles must be 64 to 256 wide");
+        static_assert(INS % NW == 0, "k-major tile must split evenly among waves");
+#pragma unroll
+        for (int q = 0; q < INS / NW; ++q) {
+            const int ins = wave * (INS / NW) + q;
+            const int k = ins * RPI + lane / CH;
+            const int logical = (lane % CH) ^ swz_k(k);
+            const int64_t gk = k0 + k, gx = x0 + 4 * logical;
+            lds_dma(gk < kend && gx < cols ? P + gk * ld + gx : zero16(), stage + ins * 256);
+        }
+    }
+
+    // DMA instructions one wave issues per K-tile
+    static constexpr int DMA_PER_TILE =
+        (BM * BK / 256 + BK * BN / 256) / NW;
+
+    __device__ __forceinline__ static void dma_tile(float *stage, const float *A, int64_t lda,
+                                                    const float *B, int64_t ldb, int64_t M,
+                                                    int64_t N, int64_t kend, int64_t m0,
+                                                    int64_t n0, int64_t k0, int wave, int lane)
+    {
+        if (A_KMAJOR)
+            dma_kmajor<BM>(stage, A, lda, kend, M, k0, m0, wave, lane);
+        else
+            dma_rows<BM>(stage, A, lda, M, kend, m0, k0, wave, lane);
+        dma_kmajor<BN>(stage + DMA_A, B, ldb, kend, N, k0, n0, wave, lane);
+    }
+
+    // s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 encoding)
+    template <int VM>
+    __device__ __forceinline__ static void wait_vm_lgkm0()
+    {
+        static_assert(VM >= 0 && VM < 64, "vmcnt out of range");
+        __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (0 << 8));
+    }
+
+    __device__ __forceinline__ static void read_frag_dma(const float *As, const float *Bs, int kk,
+                                                         int wm0, int wn0, int lane, Frag &f)
+    {
+        const int l32 = lane & 31, h = lane >> 5, h4 = h * 4;
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+            const int x = wm0 + 32 * tm + l32;
+            if (!A_KMAJOR) {
+                const f32x4 t = *reinterpret_cast<const f32x4 *>(
+                    As + x * BK + 4 * ((kk / 4 + h) ^ swz_rows(x)));
+                f.a[tm][0] = t[0];
+                f.a[tm][1] = t[1];
+                f.a[tm][2] = t[2];
+                f.a[tm][3] = t[3];
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = kk + h4 + s;
+                    f.a[tm][s] = As[k * BM + 4 * ((x >> 2) ^ swz_k(k)) + (x & 3)];
+                }
+            }
+        }
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+            const int x = wn0 + 32 * tn + l32;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = kk + h4 + s;
+                f.b[tn][s] = Bs[k * BN + 4 * ((x >> 2) ^ swz_k(k)) + (x & 3)];
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void kloop_dma(const float *As, const float *Bs, Frag &f,
+                                                     f32x16 (&acc)[TM][TN], int wm0, int wn0,
+                                                     int lane)
+    {
+#pragma unroll
+        for (int kk = 8; kk < BK; kk += 8) {
+            Frag g;
+            read_frag_dma(As, Bs, kk, wm0, wn0, lane, g);
+            mma(f, acc);
+            f = g;
+        }
+    }
+
+    __device__ __forceinline__ static void mainloop_dma(float *lds, const float *A, int64_t lda,
+                                                        const float *B, int64_t ldb, int64_t M,
+                                                        int64_t N, int64_t kbeg, int64_t kend,
+                                                        int64_t m0, int64_t n0, int64_t nk,
+                                                        f32x16 (&acc)[TM][TN])
+    {
+        constexpr int SS = DMA_A + DMA_B;  // floats per stage
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+        float *s0 = lds, *s1 = lds + SS, *s2 = lds + 2 * SS;
+        dma_tile(s0, A, lda, B, ldb, M, N, kend, m0, n0, kbeg, wave, lane);
+        dma_tile(s1, A, lda, B, ldb, M, N, kend, m0, n0, kbeg + BK, wave, lane);
+        wait_vm_lgkm0<DMA_PER_TILE>();
+        __builtin_amdgcn_s_barrier();
+        Frag f;
+        read_frag_dma(s0, s0 + DMA_A, 0, wm0, wn0, lane, f);
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            // s0: tile kt (being read), s1: tile kt + 1 (in flight), s2: free
+            dma_tile(s2, A, lda, B, ldb, M, N, kend, m0, n0, kbeg + (kt + 2) * BK, wave, lane);
+            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+            if (kt + 1 < nk) {
+                wait_vm_lgkm0<DMA_PER_TILE>();
+                __builtin_amdgcn_s_barrier();
+                Frag g;
+                read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+                mma(f, acc);
+                f = g;
+            } else {
+                mma(f, acc);
+            }
+            float *t = s0;
+            s0 = s1;
+            s1 = s2;
+            s2 = t;
+        }
+        // the loads issued past the end write zeros into the ring; let them
+        // land before the LDS is reused or the work-group ends
+        wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();
+    }
+
     // Full reduction over k in [kbeg, kend) for the block tile at (m0, n0).
     // Must be reached by every thread of the work-group (it contains
     // barriers); the trip count depends only on uniform values.
@@ -327,6 +515,11 @@ struct F32Tile {
         float *Bs = lds + 2 * A_STAGE;
         const int64_t nk = (kend - kbeg + BK - 1) / BK;
         if (nk <= 0) return;
+        if (PF == 4) {
+            static_assert(PF != 4 || LOAD == kLoadVec4, "direct LDS loads need 16-byte aligned rows");
+            mainloop_dma(lds, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc);
+            return;
+        }
         ALoader la;
         BLoader lb;
         load_a(la, A, lda, M, kend, m0, kbeg, tid, v4);

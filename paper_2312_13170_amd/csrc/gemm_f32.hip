@@ -173,7 +173,7 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
     case IDX:                                                                                      \
         return v4 ? run_gemm<F32Tile<BM, BN, BK, WM, WN, false, kLoadVec4, PF>>(M, N, K, alpha, A, lda, B, \
                                                                         ldb, beta, C, ldc, s)      \
-                  : run_gemm<F32Tile<BM, BN, BK, WM, WN, false, kLoadScalar, PF>>(M, N, K, alpha, A, lda, B, \
+                  : run_gemm<F32Tile<BM, BN, BK, WM, WN, false, kLoadScalar, (PF == 4 ? 2 : PF)>>(M, N, K, alpha, A, lda, B, \
                                                                          ldb, beta, C, ldc, s);
         LI_GEMM_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
@@ -205,7 +205,7 @@ int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                     \
     case IDX:                                                                                      \
         return v4 ? run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadVec4, PF>>(M, N, Y, S, mode, scale, SK, split_ws, s)  \
-                  : run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadScalar, PF>>(M, N, Y, S, mode, scale, SK, split_ws, s);
+                  : run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadScalar, (PF == 4 ? 2 : PF)>>(M, N, Y, S, mode, scale, SK, split_ws, s);
         LI_SYRK_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
     default:

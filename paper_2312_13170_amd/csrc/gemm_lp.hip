@@ -177,7 +177,9 @@ __device__ __forceinline__ int swz(int r, int c)
     return c ^ (((r >> 1) ^ (r >> 3)) & 3);
 }
 
-template <int BM_, int BN_, int BK_, int WM_, int WN_, int TERMS, bool FP16>
+// LAYOUT 1: rows of BK elements with XOR-swizzled 16-byte chunks;
+// LAYOUT 2: rows padded by 16 bytes, chunks in place.
+template <int BM_, int BN_, int BK_, int WM_, int WN_, int TERMS, bool FP16, int LAYOUT = 1>
 struct LpTile {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
@@ -186,7 +188,14 @@ struct LpTile {
     static constexpr int PARTS = TERMS == 3 ? 2 : 1;
     static constexpr int NTERMS = TERMS;
     static constexpr bool IS_FP16 = FP16;
-    static constexpr int A_ELEMS = BM * BK, B_ELEMS = BN * BK;
+    static constexpr int RS = LAYOUT == 2 ? BK + 8 : BK;  // LDS row stride (elements)
+    static_assert(LAYOUT == 1 || LAYOUT == 2, "unknown LDS layout");
+    // element offset of 16-byte chunk c of row r
+    __device__ __forceinline__ static int off(int r, int c)
+    {
+        return r * RS + (LAYOUT == 2 ? c : swz<CPR>(r, c)) * 8;
+    }
+    static constexpr int A_ELEMS = BM * RS, B_ELEMS = BN * RS;
     static constexpr int STAGE = PARTS * (A_ELEMS + B_ELEMS);  // bf16 elements
     static constexpr int LDS_ELEMS = 2 * STAGE;
     static constexpr int A_CH = BM * CPR / NT, B_CH = BN * CPR / NT;
@@ -263,13 +272,13 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restri
             for (int i = 0; i < T::A_CH; ++i) {
                 const int c = tid + i * NT;
                 const int r = c / CPR, cc = c % CPR;
-                *reinterpret_cast<u32x4 *>(As + r * BK + swz<CPR>(r, cc) * 8) = ra[p][i];
+                *reinterpret_cast<u32x4 *>(As + T::off(r, cc)) = ra[p][i];
             }
 #pragma unroll
             for (int i = 0; i < T::B_CH; ++i) {
                 const int c = tid + i * NT;
                 const int r = c / CPR, cc = c % CPR;
-                *reinterpret_cast<u32x4 *>(Bs + r * BK + swz<CPR>(r, cc) * 8) = rb[p][i];
+                *reinterpret_cast<u32x4 *>(Bs + T::off(r, cc)) = rb[p][i];
             }
         }
     };
@@ -293,12 +302,12 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restri
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
                     const int r = wm0 + 32 * i + l32;
-                    fa[p][i] = *reinterpret_cast<const u32x4 *>(As + p * T::A_ELEMS + r * BK + swz<CPR>(r, cidx) * 8);
+                    fa[p][i] = *reinterpret_cast<const u32x4 *>(As + p * T::A_ELEMS + T::off(r, cidx));
                 }
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const int r = wn0 + 32 * j + l32;
-                    fb[p][j] = *reinterpret_cast<const u32x4 *>(Bs + p * T::B_ELEMS + r * BK + swz<CPR>(r, cidx) * 8);
+                    fb[p][j] = *reinterpret_cast<const u32x4 *>(Bs + p * T::B_ELEMS + T::off(r, cidx));
                 }
             }
 #pragma unroll
@@ -424,9 +433,9 @@ int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alp
     switch (cfg) {
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                    \
     case IDX:                                                                                     \
-        if (prec == 3) return run_lp<LpTile<BM, BN, (BK > 32 ? 32 : BK), WM, WN, 3, false>>(L, M, N, alpha, beta, C, s); \
-        if (prec == 2) return run_lp<LpTile<BM, BN, BK, WM, WN, 1, true>>(L, M, N, alpha, beta, C, s); \
-        return run_lp<LpTile<BM, BN, BK, WM, WN, 1, false>>(L, M, N, alpha, beta, C, s);
+        if (prec == 3) return run_lp<LpTile<BM, BN, (BK > 32 ? 32 : BK), WM, WN, 3, false, PF>>(L, M, N, alpha, beta, C, s); \
+        if (prec == 2) return run_lp<LpTile<BM, BN, BK, WM, WN, 1, true, PF>>(L, M, N, alpha, beta, C, s); \
+        return run_lp<LpTile<BM, BN, BK, WM, WN, 1, false, PF>>(L, M, N, alpha, beta, C, s);
         LI_GEMM_LP_CANDIDATES(LI_CASE)
 #undef LI_CASE
     default:

@@ -21,7 +21,11 @@
     X(13, 128, 128, 32, 2, 4, 1, 3)          \
     X(14, 128, 128, 64, 2, 4, 1, 3)          \
     X(15, 128, 128, 32, 4, 4, 1, 3)          \
-    X(16, 64, 64, 32, 2, 2, 1, 3)
+    X(16, 64, 64, 32, 2, 2, 1, 3)            \
+    X(17, 128, 128, 32, 2, 4, 1, 4)          \
+    X(18, 128, 128, 32, 4, 4, 1, 4)          \
+    X(19, 64, 64, 32, 2, 2, 1, 4)            \
+    X(20, 64, 64, 64, 2, 2, 1, 4)
 
 // square block tiles only (upper-triangle enumeration)
 #define LI_SYRK_F32_CANDIDATES(X)            \
@@ -39,12 +43,20 @@
     X(11, 128, 128, 64, 4, 4, 7, 1)          \
     X(12, 128, 128, 64, 2, 4, 4, 1)          \
     X(13, 128, 128, 32, 4, 4, 7, 3)          \
-    X(14, 128, 128, 32, 2, 4, 7, 3)
+    X(14, 128, 128, 32, 2, 4, 7, 3)          \
+    X(15, 128, 128, 32, 4, 4, 7, 4)          \
+    X(16, 128, 128, 32, 2, 4, 7, 4)          \
+    X(17, 64, 64, 32, 2, 2, 1, 4)
 
-// bf16 / fp16 matrix-core GEMM on pre-rounded operands (prefetch unused)
+// bf16 / fp16 matrix-core GEMM on pre-rounded operands; the last column is
+// the LDS layout here (1: XOR-swizzled rows, 2: rows padded by 16 bytes).
+// The split-bf16 variant caps the K-tile at 32.
 #define LI_GEMM_LP_CANDIDATES(X)             \
     X(0, 256, 256, 32, 2, 4, 1, 1)           \
     X(1, 128, 128, 64, 2, 2, 1, 1)           \
     X(2, 256, 128, 32, 2, 2, 1, 1)           \
     X(3, 128, 256, 32, 2, 2, 1, 1)           \
-    X(4, 64, 64, 64, 2, 2, 1, 1)
+    X(4, 64, 64, 64, 2, 2, 1, 1)             \
+    X(5, 256, 256, 32, 2, 4, 1, 2)           \
+    X(6, 128, 128, 64, 2, 2, 1, 2)           \
+    X(7, 256, 128, 32, 2, 2, 1, 2)

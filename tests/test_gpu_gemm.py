@@ -91,8 +91,11 @@ def test_config0(li, orc):
     assert normwise(out, ref) < TOL_FP32
 
 
-@pytest.mark.parametrize("shape", [(515, 387, 301), (1000, 1030, 260), (129, 1100, 67)])
+@pytest.mark.parametrize("shape", [(515, 387, 301), (1000, 1030, 260), (129, 1100, 67),
+                                   (516, 388, 300), (260, 132, 1028)])
 def test_every_tile_shape(li, orc, shape):
+    # the last two shapes have K and N multiples of 4 (vector and direct-to-LDS
+    # loads) with ragged tiles in M, N and K
     M, N, K = shape
     A = synth.uniform_pm1(34, "A", (M, K))
     B = synth.uniform_pm1(34, "B", (K, N))
