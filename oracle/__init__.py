@@ -1,8 +1,9 @@
 """FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
 Plain loop-nest definitions (oracle/oracle.c) of what the GPU library
-computes: GEMM, the two-GEMM chain, covariance, correlation and the
-reduced-precision products.  Only the tests, the smoke check and the
+computes: GEMM, the two- and three-product chains, covariance, correlation,
+the reduced-precision products, the symmetric rank-k and rank-2k updates and
+the matrix-vector kernels (atax, bicg, mvt, gesummv).  Only the tests, the smoke check and the
 benchmark's CPU-baseline leg may import this module.  It shares no code with
 the HIP library and never imports it.
 
@@ -47,6 +48,13 @@ def _load():
         "orc_to_bf16_array": ([_i64, _p, _p], None),
         "orc_to_fp16_array": ([_i64, _p, _p], None),
         "orc_gemm_quantised": ([ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _i64, _p], ctypes.c_int),
+        "orc_mm3": ([_i64, _i64, _i64, _i64, _i64, _p, _p, _p, _p, _p, _i64, _p, _p, _p], None),
+        "orc_syrk": ([_i64, _i64, _dbl, _p, _dbl, _p, _p, _i64, _p], None),
+        "orc_syr2k": ([_i64, _i64, _dbl, _p, _p, _dbl, _p, _p, _i64, _p], None),
+        "orc_atax": ([_i64, _i64, _p, _p, _p, _p], None),
+        "orc_bicg": ([_i64, _i64, _p, _p, _p, _p, _p], None),
+        "orc_mvt": ([_i64, _i64, _p, _p, _p, _p, _p, _p, _p], None),
+        "orc_gesummv": ([_i64, _i64, _dbl, _dbl, _p, _p, _p, _p, _p], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -235,3 +243,104 @@ def normwise_error(x, ref):
     if den == 0.0:
         return float(num)
     return float(num / den)
+
+
+def mm3(A, B, C, D, rows=None):
+    """(E, F, G): E = A@B, F = C@D, G = E@F in FP64 (E, G optionally only
+    the listed rows; F always complete)."""
+    lib = _load()
+    A, B, C, D = _f32(A), _f32(B), _f32(C), _f32(D)
+    NI, NK = A.shape
+    NK2, NJ = B.shape
+    NJ2, NM = C.shape
+    NM2, NL = D.shape
+    assert NK == NK2 and NJ == NJ2 and NM == NM2
+    r, nr = _rows(rows)
+    R = nr if r is not None else NI
+    E = np.empty((R, NJ), dtype=np.float64)
+    F = np.empty((NJ, NL), dtype=np.float64)
+    G = np.empty((R, NL), dtype=np.float64)
+    lib.orc_mm3(NI, NJ, NK, NL, NM, _ptr(A), _ptr(B), _ptr(C), _ptr(D), _ptr(r), nr,
+                _ptr(E), _ptr(F), _ptr(G))
+    return E, F, G
+
+
+def syrk(A, C0=None, alpha=1.0, beta=0.0, rows=None):
+    """alpha*A@A.T + beta*C0 over the whole N x N matrix, FP64."""
+    lib = _load()
+    A = _f32(A)
+    N, K = A.shape
+    C0 = None if (C0 is None or beta == 0.0) else _f32(C0)
+    r, nr = _rows(rows)
+    out = np.empty((nr if r is not None else N, N), dtype=np.float64)
+    lib.orc_syrk(N, K, float(alpha), _ptr(A), float(beta), _ptr(C0), _ptr(r), nr, _ptr(out))
+    return out
+
+
+def syr2k(A, B, C0=None, alpha=1.0, beta=0.0, rows=None):
+    """alpha*(A@B.T + B@A.T) + beta*C0 over the whole N x N matrix, FP64."""
+    lib = _load()
+    A, B = _f32(A), _f32(B)
+    N, K = A.shape
+    assert B.shape == (N, K)
+    C0 = None if (C0 is None or beta == 0.0) else _f32(C0)
+    r, nr = _rows(rows)
+    out = np.empty((nr if r is not None else N, N), dtype=np.float64)
+    lib.orc_syr2k(N, K, float(alpha), _ptr(A), _ptr(B), float(beta), _ptr(C0), _ptr(r), nr,
+                  _ptr(out))
+    return out
+
+
+def _vec(x, n):
+    v = _f32(x).reshape(-1)
+    assert v.size == n
+    return v
+
+
+def atax(A, x):
+    """(tmp, y): tmp = A@x, y = A.T@tmp, FP64."""
+    lib = _load()
+    A = _f32(A)
+    M, N = A.shape
+    x = _vec(x, N)
+    tmp = np.empty(M, dtype=np.float64)
+    y = np.empty(N, dtype=np.float64)
+    lib.orc_atax(M, N, _ptr(A), _ptr(x), _ptr(tmp), _ptr(y))
+    return tmp, y
+
+
+def bicg(A, p, r):
+    """(q, s): q = A@p, s = A.T@r, FP64."""
+    lib = _load()
+    A = _f32(A)
+    M, N = A.shape
+    p, r = _vec(p, N), _vec(r, M)
+    q = np.empty(M, dtype=np.float64)
+    s = np.empty(N, dtype=np.float64)
+    lib.orc_bicg(M, N, _ptr(A), _ptr(p), _ptr(r), _ptr(q), _ptr(s))
+    return q, s
+
+
+def mvt(A, x1, x2, y1, y2):
+    """(x1 + A@y1, x2 + A.T@y2), FP64."""
+    lib = _load()
+    A = _f32(A)
+    M, N = A.shape
+    x1, x2, y1, y2 = _vec(x1, M), _vec(x2, N), _vec(y1, N), _vec(y2, M)
+    o1 = np.empty(M, dtype=np.float64)
+    o2 = np.empty(N, dtype=np.float64)
+    lib.orc_mvt(M, N, _ptr(A), _ptr(x1), _ptr(x2), _ptr(y1), _ptr(y2), _ptr(o1), _ptr(o2))
+    return o1, o2
+
+
+def gesummv(A, B, x, alpha=1.0, beta=1.0):
+    """(tmp, y): tmp = A@x, y = alpha*tmp + beta*B@x, FP64."""
+    lib = _load()
+    A, B = _f32(A), _f32(B)
+    M, N = A.shape
+    assert B.shape == (M, N)
+    x = _vec(x, N)
+    tmp = np.empty(M, dtype=np.float64)
+    y = np.empty(M, dtype=np.float64)
+    lib.orc_gesummv(M, N, float(alpha), float(beta), _ptr(A), _ptr(B), _ptr(x), _ptr(tmp), _ptr(y))
+    return tmp, y

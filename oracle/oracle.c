@@ -396,3 +396,180 @@ int orc_gemm_quantised(int mode, int64_t M, int64_t N, int64_t K,
     free(Bh); free(Bl);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * 3mm, the three-product chain named in Sec. VIII (polybench "3mm"):
+ *   E = A * B   (NI x NJ; A NI x NK, B NK x NJ)
+ *   F = C * D   (NJ x NL; C NJ x NM, D NM x NL)
+ *   G = E * F   (NI x NL)
+ * E and F are kept in double and returned.  rows == NULL means every row;
+ * otherwise only the listed rows of E and G are produced (F is always
+ * complete: every row of G needs all of it).
+ * ---------------------------------------------------------------------- */
+void orc_mm3(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, int64_t NM,
+             const float *A, const float *B, const float *C, const float *D,
+             const int64_t *rows, int64_t nrows, double *e_out, double *f_out, double *g_out)
+{
+    int64_t R = rows ? nrows : NI;
+    (void)NI;
+    /* F = C * D, row by row, k in increasing order */
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < NJ; ++j) {
+        double *f = f_out + j * NL;
+        for (int64_t l = 0; l < NL; ++l) f[l] = 0.0;
+        for (int64_t m = 0; m < NM; ++m) {
+            double c = (double)C[j * NM + m];
+            const float *drow = D + m * NL;
+            for (int64_t l = 0; l < NL; ++l) f[l] += c * (double)drow[l];
+        }
+    }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        double *e = e_out + r * NJ, *g = g_out + r * NL;
+        for (int64_t j = 0; j < NJ; ++j) e[j] = 0.0;
+        for (int64_t k = 0; k < NK; ++k) {
+            double a = (double)A[i * NK + k];
+            const float *brow = B + k * NJ;
+            for (int64_t j = 0; j < NJ; ++j) e[j] += a * (double)brow[j];
+        }
+        for (int64_t l = 0; l < NL; ++l) g[l] = 0.0;
+        for (int64_t j = 0; j < NJ; ++j) {
+            double ev = e[j];
+            const double *frow = f_out + j * NL;
+            for (int64_t l = 0; l < NL; ++l) g[l] += ev * frow[l];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Symmetric rank-k update (polybench "syrk", Sec. VIII), over the whole
+ * N x N matrix:
+ *   out[r][j] = alpha * sum_k A[i][k]*A[j][k] + beta*C0[i][j],  i = rows[r]
+ * A is N x K row-major.  Degenerate cases as for orc_gemm (alpha == 0: A is
+ * not read; beta == 0: C0 is not read).
+ * ---------------------------------------------------------------------- */
+void orc_syrk(int64_t N, int64_t K, double alpha, const float *A, double beta, const float *C0,
+              const int64_t *rows, int64_t nrows, double *out)
+{
+    int64_t R = rows ? nrows : N;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        for (int64_t j = 0; j < N; ++j) {
+            double s = 0.0;
+            if (alpha != 0.0)
+                for (int64_t k = 0; k < K; ++k) s += (double)A[i * K + k] * (double)A[j * K + k];
+            double v = alpha * s;
+            if (beta != 0.0) v += beta * (double)C0[i * N + j];
+            out[r * N + j] = v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Symmetric rank-2k update (polybench "syr2k", Sec. VIII), whole matrix:
+ *   out[r][j] = alpha * (sum_k A[i][k]*B[j][k] + sum_k B[i][k]*A[j][k])
+ *               + beta*C0[i][j],                              i = rows[r]
+ * A and B are N x K row-major.
+ * ---------------------------------------------------------------------- */
+void orc_syr2k(int64_t N, int64_t K, double alpha, const float *A, const float *B, double beta,
+               const float *C0, const int64_t *rows, int64_t nrows, double *out)
+{
+    int64_t R = rows ? nrows : N;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t i = rows ? rows[r] : r;
+        for (int64_t j = 0; j < N; ++j) {
+            double s1 = 0.0, s2 = 0.0;
+            if (alpha != 0.0) {
+                for (int64_t k = 0; k < K; ++k) s1 += (double)A[i * K + k] * (double)B[j * K + k];
+                for (int64_t k = 0; k < K; ++k) s2 += (double)B[i * K + k] * (double)A[j * K + k];
+            }
+            double v = alpha * (s1 + s2);
+            if (beta != 0.0) v += beta * (double)C0[i * N + j];
+            out[r * N + j] = v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Matrix-vector kernels of Sec. VIII (polybench atax, bicg, mvt, gesummv).
+ * A (and B) are M x N row-major FP32; vectors are FP32; results double.
+ * Two building blocks, each a plain loop in increasing index order:
+ *   row products     (A v)[i]  = sum_j A[i][j] * v[j]
+ *   column products  (A^T w)[j] = sum_i A[i][j] * w[i]
+ * ---------------------------------------------------------------------- */
+static void row_products(int64_t M, int64_t N, const float *A, const double *v, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < N; ++j) s += (double)A[i * N + j] * v[j];
+        out[i] = s;
+    }
+}
+
+static void column_products(int64_t M, int64_t N, const float *A, const double *w, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        double s = 0.0;
+        for (int64_t i = 0; i < M; ++i) s += (double)A[i * N + j] * w[i];
+        out[j] = s;
+    }
+}
+
+static double *to_double(int64_t n, const float *x)
+{
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) d[i] = (double)x[i];
+    return d;
+}
+
+/* ATAX: tmp = A x (length M), y = A^T tmp (length N).  tmp is used in
+ * double for the second product. */
+void orc_atax(int64_t M, int64_t N, const float *A, const float *x, double *tmp_out, double *y_out)
+{
+    double *xd = to_double(N, x);
+    row_products(M, N, A, xd, tmp_out);
+    column_products(M, N, A, tmp_out, y_out);
+    free(xd);
+}
+
+/* BICG: q = A p (length M), s = A^T r (length N). */
+void orc_bicg(int64_t M, int64_t N, const float *A, const float *p, const float *r,
+              double *q_out, double *s_out)
+{
+    double *pd = to_double(N, p), *rd = to_double(M, r);
+    row_products(M, N, A, pd, q_out);
+    column_products(M, N, A, rd, s_out);
+    free(pd);
+    free(rd);
+}
+
+/* MVT: x1 = x1_0 + A y1 (length M), x2 = x2_0 + A^T y2 (length N). */
+void orc_mvt(int64_t M, int64_t N, const float *A, const float *x1_0, const float *x2_0,
+             const float *y1, const float *y2, double *x1_out, double *x2_out)
+{
+    double *y1d = to_double(N, y1), *y2d = to_double(M, y2);
+    row_products(M, N, A, y1d, x1_out);
+    column_products(M, N, A, y2d, x2_out);
+    for (int64_t i = 0; i < M; ++i) x1_out[i] += (double)x1_0[i];
+    for (int64_t j = 0; j < N; ++j) x2_out[j] += (double)x2_0[j];
+    free(y1d);
+    free(y2d);
+}
+
+/* GESUMMV: tmp = A x, y = alpha*tmp + beta*(B x), both length M. */
+void orc_gesummv(int64_t M, int64_t N, double alpha, double beta, const float *A, const float *B,
+                 const float *x, double *tmp_out, double *y_out)
+{
+    double *xd = to_double(N, x);
+    double *bx = (double *)malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+    row_products(M, N, A, xd, tmp_out);
+    row_products(M, N, B, xd, bx);
+    for (int64_t i = 0; i < M; ++i) y_out[i] = alpha * tmp_out[i] + beta * bx[i];
+    free(bx);
+    free(xd);
+}

@@ -113,6 +113,38 @@ def mm2_inputs(NI, NJ, NK, NL, seed, alpha=1.5, beta=1.2):
                 D=uniform_pm1(seed, "D", (NI, NL)))
 
 
+def mm3_inputs(NI, NJ, NK, NL, NM, seed):
+    """3mm operands: A NI x NK, B NK x NJ, C NJ x NM, D NM x NL, U[-1, 1)."""
+    return dict(kind="mm3", NI=NI, NJ=NJ, NK=NK, NL=NL, NM=NM,
+                A=uniform_pm1(seed, "A", (NI, NK)),
+                B=uniform_pm1(seed, "B", (NK, NJ)),
+                C=uniform_pm1(seed, "C", (NJ, NM)),
+                D=uniform_pm1(seed, "D", (NM, NL)))
+
+
+def rank_update_inputs(N, K, seed, alpha=1.5, beta=1.2):
+    """syrk / syr2k operands: A, B N x K and C N x N, U[-1, 1)."""
+    return dict(kind="rank_update", N=N, K=K, alpha=alpha, beta=beta,
+                A=uniform_pm1(seed, "A", (N, K)),
+                B=uniform_pm1(seed, "B", (N, K)),
+                C=uniform_pm1(seed, "C", (N, N)))
+
+
+def matvec_inputs(M, N, seed, alpha=1.5, beta=1.2, with_b=False):
+    """Matrix-vector operands: A (and B for gesummv) M x N; vectors of the
+    column length (x, p, y1, x2) and of the row length (r, y2, x1), all
+    U[-1, 1)."""
+    d = dict(kind="matvec", M=M, N=N, alpha=alpha, beta=beta,
+             A=uniform_pm1(seed, "A", (M, N)),
+             x=uniform_pm1(seed, "x", (N,)), p=uniform_pm1(seed, "p", (N,)),
+             y1=uniform_pm1(seed, "y1", (N,)), x2=uniform_pm1(seed, "x2", (N,)),
+             r=uniform_pm1(seed, "r", (M,)), y2=uniform_pm1(seed, "y2", (M,)),
+             x1=uniform_pm1(seed, "x1", (M,)))
+    if with_b:
+        d["B"] = uniform_pm1(seed, "B", (M, N))
+    return d
+
+
 def stats_inputs(N, M, seed, eps=0.1):
     """data[i][j] = mu_j + sigma_j * z_ij, mu_j ~ U[-10,10), sigma_j ~ U[0.1,5)."""
     mu = uniform_range(seed, "mu", M, -10.0, 10.0)
