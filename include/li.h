@@ -146,6 +146,34 @@ li_status li_correlation(int64_t M, int64_t N, double eps, const float *data,
                          float *data_out, double *mean, double *stddev, float *corr,
                          void *workspace, size_t workspace_bytes, li_stream stream);
 
+/* 3mm (polybench three-product chain, Sec. VIII):
+ *   E = A * B   A: NI x NK, B: NK x NJ, E: NI x NJ (written)
+ *   F = C * D   C: NJ x NM, D: NM x NL, F: NJ x NL (written)
+ *   G = E * F   G: NI x NL (written)
+ * E and F are caller buffers and results.  No output may overlap an input
+ * or another output. */
+li_status li_mm3(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, int64_t NM,
+                 const float *A, const float *B, const float *C, const float *D,
+                 float *E, float *F, float *G, li_stream stream);
+
+/* Symmetric rank-k and rank-2k updates (polybench syrk and syr2k, Sec. VIII,
+ * where loop internalization stages their two and four operand references
+ * in local memory):
+ *   li_syrk : C = alpha * A A^T + beta * C
+ *   li_syr2k: C = alpha * (A B^T + B A^T) + beta * C
+ * A, B: N x K; C: N x N, every element updated (C need not be symmetric).
+ * The symmetric product is reduced once per pair of block tiles and each
+ * value updates both C[i][j] and C[j][i].  `workspace` (split-reduction
+ * partials) is caller-owned device memory of at least
+ * li_syrk_workspace_bytes(N, K) bytes (the same for both calls); it must not
+ * overlap A, B or C, and C must not overlap A or B. */
+size_t li_syrk_workspace_bytes(int64_t N, int64_t K);
+li_status li_syrk(int64_t N, int64_t K, float alpha, const float *A, float beta, float *C,
+                  void *workspace, size_t workspace_bytes, li_stream stream);
+li_status li_syr2k(int64_t N, int64_t K, float alpha, const float *A, const float *B,
+                   float beta, float *C, void *workspace, size_t workspace_bytes,
+                   li_stream stream);
+
 /* Split pre-pass of the LI_BF16X3 precision: hi[i] = bf16(x[i]),
  * lo[i] = bf16(x[i] - hi[i]), stored as raw bfloat16 bit patterns (uint16).
  * Also the conversion check of the 16-bit formats: with lo == NULL only hi
@@ -191,18 +219,22 @@ void li_group_plan_destroy(li_group_plan *plan);
 
 /* ---------------------------------------------------------------------
  * Tile-shape tuning.  Kernel families: LI_KERNEL_GEMM_F32 (also used by
- * 2mm), LI_KERNEL_SYRK_F32 (the covariance/correlation contraction),
- * LI_KERNEL_GEMM_LP (bf16/fp16/split products).  Each family has a fixed
+ * 2mm and 3mm), LI_KERNEL_SYRK_F32 (the covariance/correlation
+ * contraction), LI_KERNEL_GEMM_LP (bf16/fp16/split products),
+ * LI_KERNEL_SYRK_ROWS (syrk and syr2k).  Each family has a fixed
  * list of compiled tile shapes; the table maps a size bucket to one of
  * them.  The search itself (timing candidates) runs outside the library.
  * ------------------------------------------------------------------- */
-enum { LI_KERNEL_GEMM_F32 = 0, LI_KERNEL_SYRK_F32 = 1, LI_KERNEL_GEMM_LP = 2 };
+enum { LI_KERNEL_GEMM_F32 = 0, LI_KERNEL_SYRK_F32 = 1, LI_KERNEL_GEMM_LP = 2, LI_KERNEL_SYRK_ROWS = 3 };
 
 typedef struct li_tile_config {
     int32_t bm, bn, bk;     /* block tile and K-tile                    */
     int32_t waves_m, waves_n;
     int32_t split_k;        /* reduction split (1 = none)               */
-    int32_t prefetch;       /* K-tiles in flight from HBM (1 or 2)      */
+    int32_t prefetch;       /* main-loop mode 1-4 (1, 2: K-tiles in flight
+                               from HBM; 3: 2 plus operand reads pipelined
+                               across the barrier; 4: direct HBM-to-LDS
+                               loads into a three-stage ring)           */
 } li_tile_config;
 
 int32_t li_tune_num_candidates(int32_t kernel);

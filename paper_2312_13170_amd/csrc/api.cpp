@@ -215,6 +215,120 @@ li_status li_mm2(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, float alpha, fl
     return LI_OK;
 }
 
+li_status li_mm3(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, int64_t NM, const float *A,
+                 const float *B, const float *C, const float *D, float *E, float *F, float *G,
+                 li_stream stream)
+{
+    li_status s;
+    if ((s = li::check_nonneg("NI", NI)) || (s = li::check_nonneg("NJ", NJ)) ||
+        (s = li::check_nonneg("NK", NK)) || (s = li::check_nonneg("NL", NL)) ||
+        (s = li::check_nonneg("NM", NM)))
+        return s;
+    uint64_t ab, bb, cb, db, eb, fb, gb;
+    if (!li::matrix_bytes(NI, NK, 4, &ab) || !li::matrix_bytes(NK, NJ, 4, &bb) ||
+        !li::matrix_bytes(NJ, NM, 4, &cb) || !li::matrix_bytes(NM, NL, 4, &db) ||
+        !li::matrix_bytes(NI, NJ, 4, &eb) || !li::matrix_bytes(NJ, NL, 4, &fb) ||
+        !li::matrix_bytes(NI, NL, 4, &gb))
+        return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
+    // E = A B reads A, B if it has output and a reduction; likewise F = C D;
+    // G = E F reads E and F if it has output and NJ > 0.
+    const bool e_reads = NI > 0 && NJ > 0 && NK > 0, f_reads = NJ > 0 && NL > 0 && NM > 0;
+    const bool g_reads = NI > 0 && NL > 0 && NJ > 0;
+    const uint64_t ab_r = e_reads ? ab : 0, bb_r = e_reads ? bb : 0;
+    const uint64_t cb_r = f_reads ? cb : 0, db_r = f_reads ? db : 0;
+    if ((s = li::check_ptr("A", A, ab_r)) || (s = li::check_ptr("B", B, bb_r)) ||
+        (s = li::check_ptr("C", C, cb_r)) || (s = li::check_ptr("D", D, db_r)) ||
+        (s = li::check_ptr("E", E, eb)) || (s = li::check_ptr("F", F, fb)) ||
+        (s = li::check_ptr("G", G, gb)))
+        return s;
+    const Span ins[] = {{A, ab_r}, {B, bb_r}, {C, cb_r}, {D, db_r}};
+    const char *in_names[] = {"A", "B", "C", "D"};
+    const Span outs[] = {{E, eb}, {F, fb}, {G, gb}};
+    const char *out_names[] = {"E", "F", "G"};
+    for (int o = 0; o < 3; ++o) {
+        for (int i = 0; i < 4; ++i)
+            if ((s = li::check_no_overlap(out_names[o], outs[o], in_names[i], ins[i]))) return s;
+        for (int q = o + 1; q < 3; ++q)
+            if ((s = li::check_no_overlap(out_names[o], outs[o], out_names[q], outs[q]))) return s;
+    }
+    if ((s = li::ensure_device())) return s;
+    struct Step {
+        int64_t m, n, k;
+        const float *a, *b;
+        float *c;
+        const char *what;
+    } steps[] = {{NI, NJ, NK, A, B, E, "mm3 first product launch"},
+                 {NJ, NL, NM, C, D, F, "mm3 second product launch"},
+                 {NI, NL, NJ, E, F, G, "mm3 third product launch"}};
+    for (const Step &st : steps) {
+        if (st.m == 0 || st.n == 0) continue;
+        const int cfg = li::tune_pick(LI_KERNEL_GEMM_F32, st.m, st.n, st.k);
+        if ((s = launched(li::launch_gemm_f32(cfg, st.m, st.n, st.k, 1.f, st.a, st.k, st.b, st.n, 0.f,
+                                              st.c, st.n, stream),
+                          st.what)))
+            return s;
+    }
+    return LI_OK;
+}
+
+size_t li_syrk_workspace_bytes(int64_t N, int64_t K)
+{
+    if (N <= 0 || K <= 0) return 0;
+    return li::sym_rows_split_bytes(N);
+}
+
+}  // extern "C"
+
+namespace {
+
+li_status rank_update(int64_t N, int64_t K, float alpha, const float *A, const float *B, bool two,
+                      float beta, float *C, void *ws, size_t ws_bytes, li_stream stream)
+{
+    li_status s;
+    if ((s = li::check_nonneg("N", N)) || (s = li::check_nonneg("K", K))) return s;
+    uint64_t ab, cb;
+    if (!li::matrix_bytes(N, K, 4, &ab) || !li::matrix_bytes(N, N, 4, &cb))
+        return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
+    if (N > 0 && ((N + 63) / 64) * ((N + 63) / 64) > (int64_t)0x7fffffff)
+        return li::fail(LI_ERR_INVALID_SIZE, "too many output tiles");
+    const bool reads = N > 0 && K > 0 && alpha != 0.f;
+    if (!reads) ab = 0;
+    const uint64_t bb = two ? ab : 0;
+    if ((s = li::check_ptr("A", A, ab)) || (two && (s = li::check_ptr("B", B, bb))) ||
+        (s = li::check_ptr("C", C, cb)))
+        return s;
+    const size_t need = reads ? li::sym_rows_split_bytes(N) : 0;
+    if (ws_bytes < need || (need > 0 && ws == nullptr))
+        return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    const Span sA{A, ab}, sB{B, bb}, sC{C, cb}, sW{ws, need};
+    if ((s = li::check_no_overlap("C", sC, "A", sA)) || (s = li::check_no_overlap("C", sC, "B", sB)) ||
+        (s = li::check_no_overlap("workspace", sW, "A", sA)) ||
+        (s = li::check_no_overlap("workspace", sW, "B", sB)) ||
+        (s = li::check_no_overlap("workspace", sW, "C", sC)))
+        return s;
+    if ((s = li::ensure_device())) return s;
+    if (N == 0) return LI_OK;
+    const int cfg = li::tune_pick(LI_KERNEL_SYRK_ROWS, N, N, K);
+    return launched(li::launch_sym_rows(cfg, N, K, alpha, A, two ? B : nullptr, beta, C, (float *)ws, stream),
+                    two ? "syr2k launch" : "syrk launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+li_status li_syrk(int64_t N, int64_t K, float alpha, const float *A, float beta, float *C,
+                  void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    return rank_update(N, K, alpha, A, nullptr, false, beta, C, workspace, workspace_bytes, stream);
+}
+
+li_status li_syr2k(int64_t N, int64_t K, float alpha, const float *A, const float *B, float beta,
+                   float *C, void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    return rank_update(N, K, alpha, A, B, true, beta, C, workspace, workspace_bytes, stream);
+}
+
 size_t li_stats_workspace_bytes(int64_t M, int64_t N) { return li::stats_workspace_bytes(M, N); }
 
 }  // extern "C"

@@ -116,13 +116,15 @@ struct TileLoader {
 // One work-group computes a BM x BN block tile with WM x WN waves; each wave
 // owns a (BM/WM) x (BN/WN) sub-tile made of TM x TN 32x32 accumulator blocks.
 // A_KMAJOR: A element (m, k) is at A[k*lda + m] (the transposed operand of
-// the symmetric contraction); otherwise at A[m*lda + k].  B element (k, n)
-// is always at B[k*ldb + n].
+// the column-form symmetric contraction); otherwise at A[m*lda + k].
+// B_NMAJOR: B element (k, n) is at B[n*ldb + k] (the transposed operand of
+// the row-form symmetric updates A A^T); otherwise at B[k*ldb + n].
 // LOAD: kLoadScalar, kLoadVec4 or kLoadDynamic (flag passed to mainloop).
 // PF: K-tiles in flight from HBM (1: the next tile; 2: the next two; 3: the
 // next two, with LDS operand reads pipelined across the barrier; 4: direct
 // HBM-to-LDS loads into a three-stage ring, vector loads only).
-template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1>
+template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1,
+          bool B_NMAJOR = false>
 struct F32Tile {
     static_assert(PF >= 1 && PF <= 4, "prefetch mode is 1 to 4");
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
@@ -130,20 +132,21 @@ struct F32Tile {
     static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
     static_assert(TM >= 1 && TN >= 1 && BM % (32 * WM) == 0 && BN % (32 * WN) == 0, "bad wave tiling");
     static_assert(BK % 8 == 0, "BK must be a multiple of 8");
-    // LDS layouts.  Row-major A: [BM][BK+4] (16-byte reads of 4 k values;
-    // the +4 pad puts 8 consecutive rows on distinct bank groups).  K-major
-    // operands: [BK][B?+8] (lanes read consecutive m / n of one k row).
+    // LDS layouts.  Operands with k contiguous (row-major A, n-major B):
+    // [rows][BK+4] (16-byte reads of 4 k values; the +4 pad puts 8
+    // consecutive rows on distinct bank groups).  K-major operands:
+    // [BK][width+8] (lanes read consecutive m / n of one k row).
     static constexpr int A_LD = A_KMAJOR ? BM + 8 : BK + 4;
     static constexpr int A_STAGE = (A_KMAJOR ? BK : BM) * A_LD;
-    static constexpr int B_LD = BN + 8;
-    static constexpr int B_STAGE = BK * B_LD;
+    static constexpr int B_LD = B_NMAJOR ? BK + 4 : BN + 8;
+    static constexpr int B_STAGE = (B_NMAJOR ? BN : BK) * B_LD;
     // PF == 4 keeps three unpadded, XOR-swizzled stages filled by direct
     // HBM-to-LDS loads (see mainloop_dma).
     static constexpr int DMA_A = BM * BK, DMA_B = BK * BN;
     static constexpr int LDS_FLOATS = PF == 4 ? 3 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
-    using BLoader = TileLoader<BK, BN, NT, LOAD>;
+    using BLoader = TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>;
 
     __device__ __forceinline__ static void zero(f32x16 (&acc)[TM][TN])
     {
@@ -163,6 +166,32 @@ struct F32Tile {
             la.load(A, lda, kend, M, k0, m0, tid, v4);
         else
             la.load(A, lda, M, kend, m0, k0, tid, v4);
+    }
+
+    __device__ __forceinline__ static void load_b(BLoader &lb, const float *B, int64_t ldb,
+                                                  int64_t N, int64_t kend, int64_t n0, int64_t k0,
+                                                  int tid, bool v4)
+    {
+        if (B_NMAJOR)
+            lb.load(B, ldb, N, kend, n0, k0, tid, v4);
+        else
+            lb.load(B, ldb, kend, N, k0, n0, tid, v4);
+    }
+
+    // Four consecutive k values (kk + h4 .. + 3) of B column x from LDS.
+    __device__ __forceinline__ static void read_b4(const float *Bs, int kk, int h4, int x,
+                                                   float (&b)[4])
+    {
+        if (B_NMAJOR) {
+            const f32x4 t = *reinterpret_cast<const f32x4 *>(Bs + x * B_LD + kk + h4);
+            b[0] = t[0];
+            b[1] = t[1];
+            b[2] = t[2];
+            b[3] = t[3];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[s] = Bs[(kk + h4 + s) * B_LD + x];
+        }
     }
 
     // Inner loop over one LDS K-tile.
@@ -189,9 +218,7 @@ struct F32Tile {
                 }
             }
 #pragma unroll
-            for (int tn = 0; tn < TN; ++tn)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) b[tn][s] = Bs[(kk + h4 + s) * B_LD + wn0 + 32 * tn + l32];
+            for (int tn = 0; tn < TN; ++tn) read_b4(Bs, kk, h4, wn0 + 32 * tn + l32, b[tn]);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -227,9 +254,7 @@ struct F32Tile {
             }
         }
 #pragma unroll
-        for (int tn = 0; tn < TN; ++tn)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) f.b[tn][s] = Bs[(kk + h4 + s) * B_LD + wn0 + 32 * tn + l32];
+        for (int tn = 0; tn < TN; ++tn) read_b4(Bs, kk, h4, wn0 + 32 * tn + l32, f.b[tn]);
     }
 
     __device__ __forceinline__ static void mma(const Frag &f, f32x16 (&acc)[TM][TN])
@@ -273,7 +298,7 @@ struct F32Tile {
         ALoader la1;
         BLoader lb1;
         load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4);
-        lb1.load(B, ldb, kend, N, kbeg + BK, n0, tid, v4);
+        load_b(lb1, B, ldb, N, kend, n0, kbeg + BK, tid, v4);
         __syncthreads();
         Frag f;
         read_frag(As, Bs, 0, wm0, wn0, lane, f);
@@ -281,7 +306,7 @@ struct F32Tile {
         for (; kt + 2 <= nk; kt += 2) {
             const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
             load_a(la, A, lda, M, kend, m0, k2, tid, v4);
-            lb.load(B, ldb, kend, N, k2, n0, tid, v4);
+            load_b(lb, B, ldb, N, kend, n0, k2, tid, v4);
             kloop(As, Bs, f, acc, wm0, wn0, lane);
             la1.template store<A_LD>(As + A_STAGE, tid);
             lb1.template store<B_LD>(Bs + B_STAGE, tid);
@@ -293,7 +318,7 @@ struct F32Tile {
                 f = g;
             }
             load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
-            lb1.load(B, ldb, kend, N, k3, n0, tid, v4);
+            load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4);
             kloop(As + A_STAGE, Bs + B_STAGE, f, acc, wm0, wn0, lane);
             if (kt + 2 < nk) {
                 la.template store<A_LD>(As, tid);
@@ -320,8 +345,8 @@ struct F32Tile {
     // byte 16 i.  A lane may fetch any 16-byte chunk of the tile, so the
     // chunk order inside an LDS row is permuted on the global side (XOR
     // swizzle) and undone by the readers; rows stay unpadded:
-    //   row-major A [BM][BK]: physical chunk = logical ^ swz_rows(row)
-    //   k-major    [BK][W]:   physical chunk = logical ^ swz_k(k)
+    //   k-contiguous [rows][BK]: physical chunk = logical ^ swz_rows(row)
+    //   k-major      [BK][W]:    physical chunk = logical ^ swz_k(k)
     // (16 consecutive rows of one logical chunk, and the two k rows a
     // fragment read touches, fall on distinct banks).  Lanes whose chunk
     // lies outside the matrix read 16 zero bytes instead.  The ring has three
@@ -399,7 +424,10 @@ struct F32Tile {
             dma_kmajor<BM>(stage, A, lda, kend, M, k0, m0, wave, lane);
         else
             dma_rows<BM>(stage, A, lda, M, kend, m0, k0, wave, lane);
-        dma_kmajor<BN>(stage + DMA_A, B, ldb, kend, N, k0, n0, wave, lane);
+        if (B_NMAJOR)
+            dma_rows<BN>(stage + DMA_A, B, ldb, N, kend, n0, k0, wave, lane);
+        else
+            dma_kmajor<BN>(stage + DMA_A, B, ldb, kend, N, k0, n0, wave, lane);
     }
 
     // s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 encoding)
@@ -435,10 +463,19 @@ struct F32Tile {
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn) {
             const int x = wn0 + 32 * tn + l32;
+            if (B_NMAJOR) {
+                const f32x4 t = *reinterpret_cast<const f32x4 *>(
+                    Bs + x * BK + 4 * ((kk / 4 + h) ^ swz_rows(x)));
+                f.b[tn][0] = t[0];
+                f.b[tn][1] = t[1];
+                f.b[tn][2] = t[2];
+                f.b[tn][3] = t[3];
+            } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = kk + h4 + s;
-                f.b[tn][s] = Bs[k * BN + 4 * ((x >> 2) ^ swz_k(k)) + (x & 3)];
+                for (int s = 0; s < 4; ++s) {
+                    const int k = kk + h4 + s;
+                    f.b[tn][s] = Bs[k * BN + 4 * ((x >> 2) ^ swz_k(k)) + (x & 3)];
+                }
             }
         }
     }
@@ -523,7 +560,7 @@ struct F32Tile {
         ALoader la;
         BLoader lb;
         load_a(la, A, lda, M, kend, m0, kbeg, tid, v4);
-        lb.load(B, ldb, kend, N, kbeg, n0, tid, v4);
+        load_b(lb, B, ldb, N, kend, n0, kbeg, tid, v4);
         la.template store<A_LD>(As, tid);
         lb.template store<B_LD>(Bs, tid);
         if (PF == 3) {
@@ -540,19 +577,19 @@ struct F32Tile {
             ALoader la1;
             BLoader lb1;
             load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4);
-            lb1.load(B, ldb, kend, N, kbeg + BK, n0, tid, v4);
+            load_b(lb1, B, ldb, N, kend, n0, kbeg + BK, tid, v4);
             __syncthreads();
             int64_t kt = 0;
             for (; kt + 2 <= nk; kt += 2) {
                 const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
                 load_a(la, A, lda, M, kend, m0, k2, tid, v4);
-                lb.load(B, ldb, kend, N, k2, n0, tid, v4);
+                load_b(lb, B, ldb, N, kend, n0, k2, tid, v4);
                 compute(As, Bs, acc, wm0, wn0, lane);
                 la1.template store<A_LD>(As + A_STAGE, tid);
                 lb1.template store<B_LD>(Bs + B_STAGE, tid);
                 __syncthreads();
                 load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
-                lb1.load(B, ldb, kend, N, k3, n0, tid, v4);
+                load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4);
                 compute(As + A_STAGE, Bs + B_STAGE, acc, wm0, wn0, lane);
                 if (kt + 2 < nk) {
                     la.template store<A_LD>(As, tid);
@@ -573,7 +610,7 @@ struct F32Tile {
             if (more) {
                 const int64_t k1 = kbeg + (kt + 1) * BK;
                 load_a(la, A, lda, M, kend, m0, k1, tid, v4);
-                lb.load(B, ldb, kend, N, k1, n0, tid, v4);
+                load_b(lb, B, ldb, N, kend, n0, k1, tid, v4);
             }
             compute(As + cur * A_STAGE, Bs + cur * B_STAGE, acc, wm0, wn0, lane);
             if (more) {
@@ -676,10 +713,12 @@ struct F32Tile {
     // Symmetric result S (M x M): the tile at (m0, n0) with n0 >= m0 writes
     // each value to S[r][c] and S[c][r] from the same register, so S is
     // bitwise symmetric; on a diagonal tile only r <= c is written.
-    // mode 0: value * scale; mode 1: value, diagonal forced to 1.0.
+    // mode 0: value * scale; mode 1: value, diagonal forced to 1.0;
+    // mode 2: S = scale * value + beta * S at both positions (the symmetric
+    // rank updates; S is then symmetric only if it was before).
     __device__ __forceinline__ static void epilogue_syrk(const f32x16 (&acc)[TM][TN], float *S,
                                                          int64_t M, int64_t m0, int64_t n0,
-                                                         int mode, float scale)
+                                                         int mode, float scale, float beta = 0.f)
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
@@ -695,6 +734,15 @@ struct F32Tile {
                     if (row >= M || col >= M) continue;
                     if (diag_tile && row > col) continue;
                     float val = acc[i][j][v];
+                    if (mode == 2) {
+                        float *p = S + row * M + col;
+                        *p = beta != 0.f ? combine(scale, val, beta, *p) : scale * val;
+                        if (row != col) {
+                            float *q = S + col * M + row;
+                            *q = beta != 0.f ? combine(scale, val, beta, *q) : scale * val;
+                        }
+                        continue;
+                    }
                     if (mode == 0)
                         val *= scale;
                     else if (row == col)

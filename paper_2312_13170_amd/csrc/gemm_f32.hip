@@ -1,9 +1,11 @@
-// FP32 GEMM and symmetric contraction kernels (matrix cores, loop-internalised
-// reduction; see f32_tile.h for the tiling).
+// FP32 GEMM and the column-form symmetric contraction (matrix cores,
+// loop-internalised reduction; see f32_tile.h for the tiling and
+// symm_kernels.h for the symmetric kernels).
 #include <hip/hip_runtime.h>
 
 #include "f32_tile.h"
 #include "li_internal.h"
+#include "symm_kernels.h"
 #include "tiles.h"
 
 namespace li {
@@ -31,96 +33,6 @@ __global__ __launch_bounds__(T::NT) void gemm_f32_kernel(const float *__restrict
     T::epilogue_gemm(acc, C, ldc, M, N, m0, n0, alpha, beta);
 }
 
-// ---------------------------------------------------------------- SYRK
-// S = Y^T Y for Y (N samples x M features).  Only block tiles with
-// tile column >= tile row are computed; each value is written to S[r][c]
-// and S[c][r] from the same register, so S is bitwise symmetric.
-// mode 0: S *= scale; mode 1: diagonal set to 1.0.
-template <class T>
-__global__ __launch_bounds__(T::NT) void syrk_f32_kernel(const float *__restrict__ Y, int64_t M,
-                                                         int64_t N, float *__restrict__ S,
-                                                         int mode, float scale, int tiles)
-{
-    static_assert(T::BM == T::BN, "symmetric contraction needs square tiles");
-    __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
-    const int nb = tiles * (tiles + 1) / 2;
-    const int t = xcd_remap(blockIdx.x, nb);
-    int tm, tn;
-    upper_tile(t, tiles, tm, tn);
-    const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
-    f32x16 acc[T::TM][T::TN];
-    T::zero(acc);
-    // A = Y^T (element (m, k) at Y[k*M + m]), B = Y; reduction over samples.
-    T::mainloop(lds, Y, M, Y, M, M, M, 0, N, m0, n0, acc);
-    T::epilogue_syrk(acc, S, M, m0, n0, mode, scale);
-}
-
-// Split reduction for the symmetric contraction: work-group w computes the
-// partial sum of tile (w mod tiles) over the w-th K chunk and stores its raw
-// accumulators (each thread its own registers, contiguous); the reduce
-// kernel adds the chunks of a tile in chunk order (deterministic) and runs
-// the usual epilogue.  Consecutive work-groups take neighbouring tiles of
-// one chunk, so an XCD's L2 holds the Y panels they share.
-template <class T>
-__global__ __launch_bounds__(T::NT) void syrk_f32_split_kernel(const float *__restrict__ Y,
-                                                               int64_t M, int64_t N,
-                                                               float *__restrict__ part, int tiles,
-                                                               int splits, int64_t kchunk)
-{
-    __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
-    const int nb = tiles * (tiles + 1) / 2;
-    const int w = xcd_remap(blockIdx.x, nb * splits);
-    const int t = w % nb, sidx = w / nb;
-    int tm, tn;
-    upper_tile(t, tiles, tm, tn);
-    const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
-    const int64_t kbeg = (int64_t)sidx * kchunk;
-    const int64_t kend = kbeg + kchunk < N ? kbeg + kchunk : N;
-    f32x16 acc[T::TM][T::TN];
-    T::zero(acc);
-    T::mainloop(lds, Y, M, Y, M, M, M, kbeg, kend, m0, n0, acc);
-    constexpr int R = 16 * T::TM * T::TN;
-    f32x4 *dst = reinterpret_cast<f32x4 *>(part + ((int64_t)(sidx * nb + t) * T::NT + threadIdx.x) * R);
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                dst[(i * T::TN + j) * 4 + q] =
-                    f32x4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
-}
-
-template <class T>
-__global__ __launch_bounds__(T::NT) void syrk_f32_reduce_kernel(const float *__restrict__ part,
-                                                                int64_t M, float *__restrict__ S,
-                                                                int mode, float scale, int tiles,
-                                                                int splits)
-{
-    const int nb = tiles * (tiles + 1) / 2;
-    const int t = blockIdx.x;
-    int tm, tn;
-    upper_tile(t, tiles, tm, tn);
-    constexpr int R = 16 * T::TM * T::TN;
-    f32x16 acc[T::TM][T::TN];
-    T::zero(acc);
-    for (int s = 0; s < splits; ++s) {
-        const f32x4 *src =
-            reinterpret_cast<const f32x4 *>(part + ((int64_t)(s * nb + t) * T::NT + threadIdx.x) * R);
-#pragma unroll
-        for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-            for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const f32x4 x = src[(i * T::TN + j) * 4 + q];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] += x[e];
-                }
-    }
-    T::epilogue_syrk(acc, S, M, (int64_t)tm * T::BM, (int64_t)tn * T::BN, mode, scale);
-}
-
 template <class T>
 int run_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A, int64_t lda,
              const float *B, int64_t ldb, float beta, float *C, int64_t ldc, hipStream_t s)
@@ -131,29 +43,6 @@ int run_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A, int64
     const int nb = tiles_m * tiles_n;
     hipLaunchKernelGGL(gemm_f32_kernel<T>, dim3(nb), dim3(T::NT), 0, s, A, lda, B, ldb, C, ldc, M,
                        N, K, alpha, beta, tiles_m, tiles_n, group_m);
-    return (int)hipGetLastError();
-}
-
-template <class T>
-int run_syrk(int64_t M, int64_t N, const float *Y, float *S, int mode, float scale, int splits,
-             float *ws, hipStream_t s)
-{
-    const int tiles = (int)((M + T::BM - 1) / T::BM);
-    const int nb = tiles * (tiles + 1) / 2;
-    if (splits <= 1) {
-        hipLaunchKernelGGL(syrk_f32_kernel<T>, dim3(nb), dim3(T::NT), 0, s, Y, M, N, S, mode, scale,
-                           tiles);
-        return (int)hipGetLastError();
-    }
-    if (!ws) return (int)hipErrorInvalidValue;
-    int64_t kchunk = (N + splits - 1) / splits;
-    kchunk = (kchunk + T::BK - 1) / T::BK * T::BK;
-    hipLaunchKernelGGL(syrk_f32_split_kernel<T>, dim3(nb * splits), dim3(T::NT), 0, s, Y, M, N, ws,
-                       tiles, splits, kchunk);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(syrk_f32_reduce_kernel<T>, dim3(nb), dim3(T::NT), 0, s, ws, M, S, mode, scale,
-                       tiles, splits);
     return (int)hipGetLastError();
 }
 
@@ -182,17 +71,10 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
     }
 }
 
-size_t syrk_split_bytes(int64_t M)
+size_t syrk_split_bytes(int64_t n)
 {
     size_t best = 0;
-#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                   \
-    if (SK > 1) {                                                                                \
-        const int64_t t = (M + BM - 1) / BM;                                                     \
-        const size_t b = (size_t)SK * (size_t)(t * (t + 1) / 2) * BM * BN * sizeof(float);       \
-        if (b > best) best = b;                                                                  \
-    }
-    LI_SYRK_F32_CANDIDATES(LI_CASE)
-#undef LI_CASE
+    LI_SYRK_F32_CANDIDATES(LI_SYM_SPLIT_BYTES)
     return best;
 }
 
@@ -201,11 +83,12 @@ int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int
 {
     hipStream_t s = (hipStream_t)stream;
     const bool v4 = (M % 4 == 0 && aligned16(Y));
+    const SymArgs a{Y, nullptr, M, M, N, S, mode, scale, 0.f, 1};
     switch (cfg) {
-#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                     \
-    case IDX:                                                                                      \
-        return v4 ? run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadVec4, PF>>(M, N, Y, S, mode, scale, SK, split_ws, s)  \
-                  : run_syrk<F32Tile<BM, BN, BK, WM, WN, true, kLoadScalar, (PF == 4 ? 2 : PF)>>(M, N, Y, S, mode, scale, SK, split_ws, s);
+#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                      \
+    case IDX:                                                                                       \
+        return v4 ? run_sym<F32Tile<BM, BN, BK, WM, WN, true, kLoadVec4, PF>, kSymCols>(a, SK, split_ws, s) \
+                  : run_sym<F32Tile<BM, BN, BK, WM, WN, true, kLoadScalar, (PF == 4 ? 2 : PF)>, kSymCols>(a, SK, split_ws, s);
         LI_SYRK_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
     default:

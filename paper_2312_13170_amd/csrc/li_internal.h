@@ -61,6 +61,13 @@ size_t syrk_split_bytes(int64_t M);
 int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode,
                     float scale, float *split_ws, void *stream);
 
+// Row-form symmetric updates (symm_rows.hip): C = alpha*P + beta*C with
+// P = A A^T (B == NULL) or A B^T + B A^T; A, B n x k, C n x n.  Candidates
+// with split_k > 1 need split_ws of sym_rows_split_bytes(n) bytes.
+size_t sym_rows_split_bytes(int64_t n);
+int launch_sym_rows(int cfg, int64_t n, int64_t k, float alpha, const float *A, const float *B,
+                    float beta, float *C, float *split_ws, void *stream);
+
 // Column statistics (FP64) and centring / normalisation.  The rows of a
 // column are cut into nsplit chunks of rows_per_split rows (stats.hip).
 constexpr int kStatThreads = 256;

@@ -60,3 +60,19 @@
     X(5, 256, 256, 32, 2, 4, 1, 2)           \
     X(6, 128, 128, 64, 2, 2, 1, 2)           \
     X(7, 256, 128, 32, 2, 2, 1, 2)
+
+// Row-form symmetric updates (syrk A A^T, syr2k A B^T + B A^T): square block
+// tiles, operands with k contiguous.
+#define LI_SYRK_ROWS_CANDIDATES(X)           \
+    X(0, 128, 128, 32, 2, 2, 1, 1)           \
+    X(1, 64, 64, 32, 2, 2, 1, 1)             \
+    X(2, 128, 128, 32, 2, 4, 1, 3)           \
+    X(3, 128, 128, 32, 2, 4, 2, 3)           \
+    X(4, 128, 128, 32, 2, 4, 4, 3)           \
+    X(5, 128, 128, 32, 4, 4, 4, 2)           \
+    X(6, 128, 128, 32, 4, 4, 7, 2)           \
+    X(7, 128, 128, 32, 2, 4, 7, 3)           \
+    X(8, 128, 128, 32, 4, 4, 4, 4)           \
+    X(9, 64, 64, 32, 2, 2, 4, 2)             \
+    X(10, 64, 64, 32, 2, 2, 1, 3)            \
+    X(11, 128, 128, 32, 4, 4, 2, 4)

@@ -18,9 +18,10 @@ namespace {
 const TileCfg kGemmF32[] = {LI_GEMM_F32_CANDIDATES(LI_ENTRY)};
 const TileCfg kSyrkF32[] = {LI_SYRK_F32_CANDIDATES(LI_ENTRY)};
 const TileCfg kGemmLp[] = {LI_GEMM_LP_CANDIDATES(LI_ENTRY)};
+const TileCfg kSyrkRows[] = {LI_SYRK_ROWS_CANDIDATES(LI_ENTRY)};
 #undef LI_ENTRY
 
-constexpr int kFamilies = 3;
+constexpr int kFamilies = 4;
 constexpr int kBuckets = 64;
 
 const TileCfg *family(int k, int *n)
@@ -35,6 +36,9 @@ const TileCfg *family(int k, int *n)
     case LI_KERNEL_GEMM_LP:
         *n = (int)(sizeof(kGemmLp) / sizeof(kGemmLp[0]));
         return kGemmLp;
+    case LI_KERNEL_SYRK_ROWS:
+        *n = (int)(sizeof(kSyrkRows) / sizeof(kSyrkRows[0]));
+        return kSyrkRows;
     default:
         *n = 0;
         return nullptr;
@@ -63,6 +67,16 @@ int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
         const int64_t t128 = ceil_div(M, 128);
         if (t128 * (t128 + 1) / 2 >= cus) return 0;
         return 2;
+    }
+    if (kernel == LI_KERNEL_SYRK_ROWS) {
+        // M is the order of C, K the reduction length: split the reduction
+        // until the upper 128-tiles times the split cover the chip
+        const int64_t t128 = ceil_div(M, 128), up = t128 * (t128 + 1) / 2;
+        if (up >= cus) return 2;
+        if (up * 2 >= cus && K >= 512) return 3;
+        if (up * 4 >= cus && K >= 1024) return 4;
+        if (K >= 1024) return 7;
+        return 9;
     }
     if (kernel == LI_KERNEL_GEMM_LP) {
         if (ceil_div(M, 256) * ceil_div(N, 256) >= cus) return 0;

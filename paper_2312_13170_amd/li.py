@@ -35,7 +35,7 @@ LI_FP32, LI_BF16, LI_FP16, LI_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp32": LI_FP32, "bf16": LI_BF16, "fp16": LI_FP16, "bf16x3": LI_BF16X3}
 
 LI_PROBLEM_GEMM, LI_PROBLEM_COVARIANCE = 0, 1
-LI_KERNEL_GEMM_F32, LI_KERNEL_SYRK_F32, LI_KERNEL_GEMM_LP = 0, 1, 2
+LI_KERNEL_GEMM_F32, LI_KERNEL_SYRK_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_SYRK_ROWS = 0, 1, 2, 3
 
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -65,6 +65,10 @@ _SIGS = {
     "li_gemm_ex": ([_i64, _i64, _i64, _f32, _p, _p, _f32, _p, _i32, _p, _sz, _p], _i32),
     "li_gemm_form": ([_i32, _i64, _i64, _i64, _f32, _p, _p, _f32, _p, _p], _i32),
     "li_mm2": ([_i64, _i64, _i64, _i64, _f32, _f32, _p, _p, _p, _p, _p, _p], _i32),
+    "li_mm3": ([_i64, _i64, _i64, _i64, _i64, _p, _p, _p, _p, _p, _p, _p, _p], _i32),
+    "li_syrk_workspace_bytes": ([_i64, _i64], _sz),
+    "li_syrk": ([_i64, _i64, _f32, _p, _f32, _p, _p, _sz, _p], _i32),
+    "li_syr2k": ([_i64, _i64, _f32, _p, _p, _f32, _p, _p, _sz, _p], _i32),
     "li_stats_workspace_bytes": ([_i64, _i64], _sz),
     "li_covariance": ([_i64, _i64, _p, _p, _p, _p, _p, _sz, _p], _i32),
     "li_correlation": ([_i64, _i64, _f64, _p, _p, _p, _p, _p, _p, _sz, _p], _i32),
@@ -162,6 +166,25 @@ def li_gemm_form(form, M, N, K, alpha, A, B, beta, C, stream=None) -> None:
 def li_mm2(NI, NJ, NK, NL, alpha, beta, A, B, tmp, C, D, stream=None) -> None:
     _check(_lib.li_mm2(NI, NJ, NK, NL, alpha, beta, _ptr(A), _ptr(B), _ptr(tmp), _ptr(C), _ptr(D),
                        _stream(stream)))
+
+
+def li_mm3(NI, NJ, NK, NL, NM, A, B, C, D, E, F, G, stream=None) -> None:
+    _check(_lib.li_mm3(NI, NJ, NK, NL, NM, _ptr(A), _ptr(B), _ptr(C), _ptr(D), _ptr(E), _ptr(F),
+                       _ptr(G), _stream(stream)))
+
+
+def li_syrk_workspace_bytes(N, K) -> int:
+    return int(_lib.li_syrk_workspace_bytes(N, K))
+
+
+def li_syrk(N, K, alpha, A, beta, C, workspace, workspace_bytes=None, stream=None) -> None:
+    _check(_lib.li_syrk(N, K, alpha, _ptr(A), beta, _ptr(C), _ptr(workspace),
+                        _ws_bytes(workspace, workspace_bytes), _stream(stream)))
+
+
+def li_syr2k(N, K, alpha, A, B, beta, C, workspace, workspace_bytes=None, stream=None) -> None:
+    _check(_lib.li_syr2k(N, K, alpha, _ptr(A), _ptr(B), beta, _ptr(C), _ptr(workspace),
+                         _ws_bytes(workspace, workspace_bytes), _stream(stream)))
 
 
 def li_stats_workspace_bytes(M, N) -> int:

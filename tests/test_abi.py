@@ -92,6 +92,41 @@ def test_covariance_argument_rules(li):
                               FAKE + 8 * xb, ws, None) == li.LI_ERR_INVALID_SIZE
 
 
+def test_rank_update_argument_rules(li):
+    lib = li._lib
+    N, K = 16, 8
+    ab, cb = 4 * N * K, 4 * N * N
+    ws = lib.li_syrk_workspace_bytes(N, K)
+    assert ws > 0 and lib.li_syrk_workspace_bytes(0, K) == 0
+    W = FAKE + (1 << 24)
+    assert lib.li_syrk(-1, K, 1.0, FAKE, 0.0, FAKE + ab, W, ws, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_syrk(N, K, 1.0, None, 0.0, FAKE + ab, W, ws, None) == li.LI_ERR_NULL_POINTER
+    # C inside A
+    assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + 4, W, ws, None) == li.LI_ERR_OVERLAP
+    # workspace too small, and overlapping C
+    assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + ab, W, ws - 4, None) == li.LI_ERR_WORKSPACE
+    assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + ab, FAKE + ab + 8, ws, None) == li.LI_ERR_OVERLAP
+    # syr2k: B NULL, C overlapping B
+    assert lib.li_syr2k(N, K, 1.0, FAKE, None, 0.0, FAKE + 2 * ab, W, ws, None) == li.LI_ERR_NULL_POINTER
+    assert lib.li_syr2k(N, K, 1.0, FAKE, FAKE + ab, 0.0, FAKE + ab + 4, W, ws, None) == li.LI_ERR_OVERLAP
+    # alpha == 0: operands are not read, so NULL A / B and no workspace pass
+    # validation (the call then needs the device, absent here)
+    st = lib.li_syr2k(N, K, 0.0, None, None, 1.0, FAKE + cb, None, 0, None)
+    assert st in (li.LI_OK, li.LI_ERR_UNSUPPORTED_DEVICE)
+
+
+def test_mm3_argument_rules(li):
+    lib = li._lib
+    n = 16
+    b = 4 * n * n
+    A, B, C, D, E, F, G = (FAKE + i * b for i in range(7))
+    assert lib.li_mm3(n, n, n, n, -1, A, B, C, D, E, F, G, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_mm3(n, n, n, n, n, A, B, C, D, None, F, G, None) == li.LI_ERR_NULL_POINTER
+    # G overlapping F, E overlapping D
+    assert lib.li_mm3(n, n, n, n, n, A, B, C, D, E, F, F + 4, None) == li.LI_ERR_OVERLAP
+    assert lib.li_mm3(n, n, n, n, n, A, B, C, D, D + 8, F, G, None) == li.LI_ERR_OVERLAP
+
+
 def test_gemm_form_validation(li):
     lib = li._lib
     assert lib.li_gemm_form(5, 8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, None) == li.LI_ERR_BAD_ENUM
@@ -110,13 +145,14 @@ def test_precision_enum_and_workspace(li):
 
 
 def test_tuning_table(li):
-    for k in (li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_GEMM_LP):
+    for k in (li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_GEMM_LP,
+              li.LI_KERNEL_SYRK_ROWS):
         n = li.li_tune_num_candidates(k)
         assert n >= 3
         for i in range(n):
             c = li.li_tune_candidate(k, i)
             assert c["bm"] % 32 == 0 and c["bn"] % 32 == 0 and c["bk"] % 8 == 0
-            if k == li.LI_KERNEL_SYRK_F32:
+            if k in (li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_SYRK_ROWS):
                 assert c["bm"] == c["bn"]
     assert li.li_tune_bucket(2048, 2048, 2048) == 12
     assert li.li_tune_bucket(1, 1, 1) == 1
