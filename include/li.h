@@ -174,6 +174,35 @@ li_status li_syr2k(int64_t N, int64_t K, float alpha, const float *A, const floa
                    float beta, float *C, void *workspace, size_t workspace_bytes,
                    li_stream stream);
 
+/* Matrix-vector kernels (polybench atax, bicg, mvt and gesummv, Sec. VIII;
+ * their per-row sums are detect-reduction sites, Sec. VI-B).  A (and B) are
+ * M x N, row-major FP32; vectors are FP32 of the stated lengths.
+ *   li_atax   : tmp = A x (M), y = A^T tmp (N)         x: N
+ *   li_bicg   : q = A p (M),   s = A^T r (N)           p: N, r: M
+ *   li_mvt    : x1 += A y1 (M), x2 += A^T y2 (N)       y1: N, y2: M
+ *   li_gesummv: tmp = A x (M), y = alpha tmp + beta B x (M)   x: N
+ * Each matrix is streamed from HBM once per call: a row's product with the
+ * vector and its contribution to the column sums come from the same load
+ * (atax: in one pass for N <= 16384, else two).  Sums run in FP32 in a
+ * fixed order, so results are deterministic.  A and B are read whenever
+ * M, N > 0 (also for alpha or beta == 0).  With M or N == 0 the sums are
+ * empty: outputs that are written become 0, mvt leaves x1 and x2 as they
+ * are.  `workspace` (column and row partial sums) is caller-owned device
+ * memory of at least li_matvec_workspace_bytes(M, N) bytes; outputs must
+ * not overlap inputs, each other or the workspace. */
+size_t li_matvec_workspace_bytes(int64_t M, int64_t N);
+li_status li_atax(int64_t M, int64_t N, const float *A, const float *x, float *tmp, float *y,
+                  void *workspace, size_t workspace_bytes, li_stream stream);
+li_status li_bicg(int64_t M, int64_t N, const float *A, const float *p, const float *r,
+                  float *q, float *s, void *workspace, size_t workspace_bytes,
+                  li_stream stream);
+li_status li_mvt(int64_t M, int64_t N, const float *A, const float *y1, const float *y2,
+                 float *x1, float *x2, void *workspace, size_t workspace_bytes,
+                 li_stream stream);
+li_status li_gesummv(int64_t M, int64_t N, float alpha, float beta, const float *A,
+                     const float *B, const float *x, float *tmp, float *y, void *workspace,
+                     size_t workspace_bytes, li_stream stream);
+
 /* Split pre-pass of the LI_BF16X3 precision: hi[i] = bf16(x[i]),
  * lo[i] = bf16(x[i] - hi[i]), stored as raw bfloat16 bit patterns (uint16).
  * Also the conversion check of the 16-bit formats: with lo == NULL only hi

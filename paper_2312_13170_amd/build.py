@@ -19,7 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["validate.cpp", "tune.cpp", "api.cpp", "gemm_f32.hip", "stats.hip", "gemm_lp.hip",
-           "grouped.hip", "gemm_forms.hip", "symm_rows.hip"]
+           "grouped.hip", "gemm_forms.hip", "symm_rows.hip",
+           "matvec.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",

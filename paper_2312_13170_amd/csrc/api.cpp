@@ -401,6 +401,129 @@ li_status li_correlation(int64_t M, int64_t N, double eps, const float *data, fl
                         workspace_bytes, stream);
 }
 
+size_t li_matvec_workspace_bytes(int64_t M, int64_t N) { return li::matvec_workspace_bytes(M, N); }
+
+}  // extern "C"
+
+namespace {
+
+struct Vec {
+    const char *name;
+    const void *p;
+    int64_t n;  // elements (FP32)
+};
+
+// M * N, saturated (sizes are non-negative here; an oversized product is
+// rejected by the matrix extent check)
+int64_t elems(int64_t M, int64_t N)
+{
+    if (M <= 0 || N <= 0) return 0;
+    return M > INT64_MAX / N ? INT64_MAX : M * N;
+}
+
+// Validation and launch shared by the matrix-vector entry points.  ins and
+// outs list every operand the call reads or writes (matrices as vectors of
+// M*N elements); `zero_outs` are set to 0 when M or N is 0.
+li_status matvec_common(int op, int64_t M, int64_t N, const Vec *ins, int nin, const Vec *outs,
+                        int nout, const float *A, const float *B, const float *v1,
+                        const float *v2, float *o1, float *o2, float alpha, float beta, void *ws,
+                        size_t ws_bytes, float *const *zero_outs, const int64_t *zero_lens,
+                        int nzero, li_stream stream)
+{
+    li_status s;
+    if ((s = li::check_nonneg("M", M)) || (s = li::check_nonneg("N", N))) return s;
+    uint64_t mb;
+    if (!li::matrix_bytes(M, N, 4, &mb)) return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
+    const bool work = M > 0 && N > 0;
+    Span in_s[4], out_s[3];
+    for (int i = 0; i < nin; ++i) {
+        uint64_t b = 0;
+        if (!li::matrix_bytes(ins[i].n, 1, 4, &b)) return li::fail(LI_ERR_INVALID_SIZE, "extent too large");
+        if (!work) b = 0;  // nothing is read
+        in_s[i] = Span{ins[i].p, b};
+        if ((s = li::check_ptr(ins[i].name, ins[i].p, b))) return s;
+    }
+    for (int i = 0; i < nout; ++i) {
+        uint64_t b = 0;
+        if (!li::matrix_bytes(outs[i].n, 1, 4, &b)) return li::fail(LI_ERR_INVALID_SIZE, "extent too large");
+        out_s[i] = Span{outs[i].p, b};
+        if ((s = li::check_ptr(outs[i].name, outs[i].p, b))) return s;
+    }
+    const size_t need = work ? li::matvec_workspace_bytes(M, N) : 0;
+    if (ws_bytes < need || (need > 0 && ws == nullptr))
+        return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    const Span sW{ws, need};
+    for (int o = 0; o < nout; ++o) {
+        for (int i = 0; i < nin; ++i)
+            if ((s = li::check_no_overlap(outs[o].name, out_s[o], ins[i].name, in_s[i]))) return s;
+        for (int q = o + 1; q < nout; ++q)
+            if ((s = li::check_no_overlap(outs[o].name, out_s[o], outs[q].name, out_s[q]))) return s;
+        if ((s = li::check_no_overlap("workspace", sW, outs[o].name, out_s[o]))) return s;
+    }
+    for (int i = 0; i < nin; ++i)
+        if ((s = li::check_no_overlap("workspace", sW, ins[i].name, in_s[i]))) return s;
+    if ((s = li::ensure_device())) return s;
+    if (!work) {
+        for (int z = 0; z < nzero; ++z)
+            if ((s = launched(li::launch_fill(zero_outs[z], zero_lens[z], 0.f, stream), "fill launch")))
+                return s;
+        return LI_OK;
+    }
+    return launched(li::launch_matvec(op, M, N, A, B, v1, v2, o1, o2, alpha, beta, ws, stream),
+                    "matrix-vector launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+li_status li_atax(int64_t M, int64_t N, const float *A, const float *x, float *tmp, float *y,
+                  void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    const Vec ins[] = {{"A", A, elems(M, N)}, {"x", x, N}};
+    const Vec outs[] = {{"tmp", tmp, M}, {"y", y, N}};
+    float *const zo[] = {tmp, y};
+    const int64_t zl[] = {M, N};
+    if (M < 0 || N < 0) return li::check_nonneg(M < 0 ? "M" : "N", M < 0 ? M : N);
+    return matvec_common(li::kMvAtax, M, N, ins, 2, outs, 2, A, nullptr, x, nullptr, tmp, y, 0.f,
+                         0.f, workspace, workspace_bytes, zo, zl, 2, stream);
+}
+
+li_status li_bicg(int64_t M, int64_t N, const float *A, const float *p, const float *r, float *q,
+                  float *s, void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    const Vec ins[] = {{"A", A, elems(M, N)}, {"p", p, N}, {"r", r, M}};
+    const Vec outs[] = {{"q", q, M}, {"s", s, N}};
+    float *const zo[] = {q, s};
+    const int64_t zl[] = {M, N};
+    if (M < 0 || N < 0) return li::check_nonneg(M < 0 ? "M" : "N", M < 0 ? M : N);
+    return matvec_common(li::kMvBicg, M, N, ins, 3, outs, 2, A, nullptr, p, r, q, s, 0.f, 0.f,
+                         workspace, workspace_bytes, zo, zl, 2, stream);
+}
+
+li_status li_mvt(int64_t M, int64_t N, const float *A, const float *y1, const float *y2, float *x1,
+                 float *x2, void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    const Vec ins[] = {{"A", A, elems(M, N)}, {"y1", y1, N}, {"y2", y2, M}};
+    const Vec outs[] = {{"x1", x1, M}, {"x2", x2, N}};
+    if (M < 0 || N < 0) return li::check_nonneg(M < 0 ? "M" : "N", M < 0 ? M : N);
+    return matvec_common(li::kMvMvt, M, N, ins, 3, outs, 2, A, nullptr, y1, y2, x1, x2, 0.f, 0.f,
+                         workspace, workspace_bytes, nullptr, nullptr, 0, stream);
+}
+
+li_status li_gesummv(int64_t M, int64_t N, float alpha, float beta, const float *A, const float *B,
+                     const float *x, float *tmp, float *y, void *workspace, size_t workspace_bytes,
+                     li_stream stream)
+{
+    const Vec ins[] = {{"A", A, elems(M, N)}, {"B", B, elems(M, N)}, {"x", x, N}};
+    const Vec outs[] = {{"tmp", tmp, M}, {"y", y, M}};
+    float *const zo[] = {tmp, y};
+    const int64_t zl[] = {M, M};
+    if (M < 0 || N < 0) return li::check_nonneg(M < 0 ? "M" : "N", M < 0 ? M : N);
+    return matvec_common(li::kMvGesummv, M, N, ins, 3, outs, 2, A, B, x, nullptr, tmp, y, alpha, beta,
+                         workspace, workspace_bytes, zo, zl, 2, stream);
+}
+
 li_status li_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, li_precision p,
                      li_stream stream)
 {

@@ -82,6 +82,19 @@ size_t stats_workspace_bytes(int64_t M, int64_t N);  // statistics + contraction
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
                  int correlation, double eps, void *ws, void *stream);
 
+// Matrix-vector kernels (matvec.hip), A (and B) M x N, M, N >= 1:
+//   kMvAtax    v1 = x; o1 = tmp = A x; o2 = y = A^T tmp
+//   kMvBicg    v1 = p, v2 = r; o1 = q = A p; o2 = s = A^T r
+//   kMvMvt     v1 = y1, v2 = y2; o1 = x1 += A y1; o2 = x2 += A^T y2
+//   kMvGesummv v1 = x; o1 = tmp = A x; o2 = y = alpha tmp + beta B x
+enum { kMvAtax = 0, kMvBicg = 1, kMvMvt = 2, kMvGesummv = 3 };
+size_t matvec_workspace_bytes(int64_t M, int64_t N);
+int launch_matvec(int op, int64_t M, int64_t N, const float *A, const float *B, const float *v1,
+                  const float *v2, float *o1, float *o2, float alpha, float beta, void *ws,
+                  void *stream);
+// p[0..n) = v (a kernel, so a stream capture records no memset node)
+int launch_fill(float *p, int64_t n, float v, void *stream);
+
 // Scalar work-item forms of the GEMM (gemm_forms.hip).
 int launch_gemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
                      const float *B, float beta, float *C, void *stream);

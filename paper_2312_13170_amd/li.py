@@ -69,6 +69,11 @@ _SIGS = {
     "li_syrk_workspace_bytes": ([_i64, _i64], _sz),
     "li_syrk": ([_i64, _i64, _f32, _p, _f32, _p, _p, _sz, _p], _i32),
     "li_syr2k": ([_i64, _i64, _f32, _p, _p, _f32, _p, _p, _sz, _p], _i32),
+    "li_matvec_workspace_bytes": ([_i64, _i64], _sz),
+    "li_atax": ([_i64, _i64, _p, _p, _p, _p, _p, _sz, _p], _i32),
+    "li_bicg": ([_i64, _i64, _p, _p, _p, _p, _p, _p, _sz, _p], _i32),
+    "li_mvt": ([_i64, _i64, _p, _p, _p, _p, _p, _p, _sz, _p], _i32),
+    "li_gesummv": ([_i64, _i64, _f32, _f32, _p, _p, _p, _p, _p, _p, _sz, _p], _i32),
     "li_stats_workspace_bytes": ([_i64, _i64], _sz),
     "li_covariance": ([_i64, _i64, _p, _p, _p, _p, _p, _sz, _p], _i32),
     "li_correlation": ([_i64, _i64, _f64, _p, _p, _p, _p, _p, _p, _sz, _p], _i32),
@@ -185,6 +190,32 @@ def li_syrk(N, K, alpha, A, beta, C, workspace, workspace_bytes=None, stream=Non
 def li_syr2k(N, K, alpha, A, B, beta, C, workspace, workspace_bytes=None, stream=None) -> None:
     _check(_lib.li_syr2k(N, K, alpha, _ptr(A), _ptr(B), beta, _ptr(C), _ptr(workspace),
                          _ws_bytes(workspace, workspace_bytes), _stream(stream)))
+
+
+def li_matvec_workspace_bytes(M, N) -> int:
+    return int(_lib.li_matvec_workspace_bytes(M, N))
+
+
+def li_atax(M, N, A, x, tmp, y, workspace, workspace_bytes=None, stream=None) -> None:
+    _check(_lib.li_atax(M, N, _ptr(A), _ptr(x), _ptr(tmp), _ptr(y), _ptr(workspace),
+                        _ws_bytes(workspace, workspace_bytes), _stream(stream)))
+
+
+def li_bicg(M, N, A, p, r, q, s, workspace, workspace_bytes=None, stream=None) -> None:
+    _check(_lib.li_bicg(M, N, _ptr(A), _ptr(p), _ptr(r), _ptr(q), _ptr(s), _ptr(workspace),
+                        _ws_bytes(workspace, workspace_bytes), _stream(stream)))
+
+
+def li_mvt(M, N, A, y1, y2, x1, x2, workspace, workspace_bytes=None, stream=None) -> None:
+    _check(_lib.li_mvt(M, N, _ptr(A), _ptr(y1), _ptr(y2), _ptr(x1), _ptr(x2), _ptr(workspace),
+                       _ws_bytes(workspace, workspace_bytes), _stream(stream)))
+
+
+def li_gesummv(M, N, alpha, beta, A, B, x, tmp, y, workspace, workspace_bytes=None,
+               stream=None) -> None:
+    _check(_lib.li_gesummv(M, N, alpha, beta, _ptr(A), _ptr(B), _ptr(x), _ptr(tmp), _ptr(y),
+                           _ptr(workspace), _ws_bytes(workspace, workspace_bytes),
+                           _stream(stream)))
 
 
 def li_stats_workspace_bytes(M, N) -> int:

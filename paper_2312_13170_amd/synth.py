@@ -29,19 +29,26 @@ _M2 = np.uint64(0x94D049BB133111EB)
 
 
 def _mix(z: np.ndarray) -> np.ndarray:
-    z = np.asarray(z, dtype=np.uint64)
+    """SplitMix64 output function, in place on a fresh uint64 array."""
+    z = np.array(z, dtype=np.uint64, copy=True)
+    t = np.empty_like(z)
     with np.errstate(over="ignore"):
-        z = (z ^ (z >> np.uint64(30))) * _M1
-        z = (z ^ (z >> np.uint64(27))) * _M2
-    return z ^ (z >> np.uint64(31))
+        for shift, mul in ((30, _M1), (27, _M2)):
+            np.right_shift(z, np.uint64(shift), out=t)
+            np.bitwise_xor(z, t, out=z)
+            np.multiply(z, mul, out=z)
+        np.right_shift(z, np.uint64(31), out=t)
+        np.bitwise_xor(z, t, out=z)
+    return z
 
 
 def splitmix64(key: int, n: int, offset: int = 0) -> np.ndarray:
     """Outputs offset .. offset+n-1 of SplitMix64 started from state `key`."""
     ctr = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
     with np.errstate(over="ignore"):
-        state = np.uint64(key & 0xFFFFFFFFFFFFFFFF) + ctr * GAMMA
-    return _mix(state)
+        np.multiply(ctr, GAMMA, out=ctr)
+        np.add(ctr, np.uint64(key & 0xFFFFFFFFFFFFFFFF), out=ctr)
+    return _mix(ctr)
 
 
 def stream_key(seed: int, name: str) -> int:
@@ -60,10 +67,21 @@ def uniform53(x: np.ndarray) -> np.ndarray:
 
 
 def uniform_pm1(seed: int, name: str, shape) -> np.ndarray:
-    """float32 values in [-1, 1) on a 2**-23 grid."""
+    """float32 values in [-1, 1) on a 2**-23 grid: 2 * uniform24 - 1, formed
+    as (k - 2**23) * 2**-23 with k = x >> 40 (every step exact in float32),
+    in chunks of the stream so large matrices need little extra memory."""
     n = int(np.prod(shape)) if len(shape) else 1
-    u = uniform24(splitmix64(stream_key(seed, name), n))
-    return (2.0 * u - 1.0).astype(np.float32).reshape(shape)
+    key = stream_key(seed, name)
+    out = np.empty(n, dtype=np.float32)
+    chunk = 1 << 22
+    for s0 in range(0, n, chunk):
+        m = min(chunk, n - s0)
+        k = (splitmix64(key, m, offset=s0) >> np.uint64(40)).astype(np.int32)
+        k -= 1 << 23
+        view = out[s0:s0 + m]
+        view[:] = k
+        view *= np.float32(2.0 ** -23)
+    return out.reshape(shape)
 
 
 def uniform_range(seed: int, name: str, n: int, lo: float, hi: float) -> np.ndarray:

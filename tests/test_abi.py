@@ -224,3 +224,26 @@ def test_tune_table_save_load(li, tmp_path):
     finally:
         li.li_tune_set(k, b1, old1)
         li.li_tune_set(k, b2, old2)
+
+
+def test_matvec_argument_rules(li):
+    lib = li._lib
+    M, N = 16, 8
+    ab = 4 * M * N
+    ws = lib.li_matvec_workspace_bytes(M, N)
+    assert ws > 0 and lib.li_matvec_workspace_bytes(0, N) == 0
+    W = FAKE + (1 << 24)
+    x, t, y = FAKE + ab, FAKE + ab + 4096, FAKE + ab + 8192
+    assert lib.li_atax(-1, N, FAKE, x, t, y, W, ws, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_atax(M, N, None, x, t, y, W, ws, None) == li.LI_ERR_NULL_POINTER
+    assert lib.li_atax(M, N, FAKE, x, x + 4, y, W, ws, None) == li.LI_ERR_OVERLAP
+    assert lib.li_atax(M, N, FAKE, x, t, y, W, ws - 4, None) == li.LI_ERR_WORKSPACE
+    assert lib.li_atax(M, N, FAKE, x, t, y, FAKE + 8, ws, None) == li.LI_ERR_OVERLAP
+    # mvt: x1 overlapping x2 (both in/out)
+    assert lib.li_mvt(M, N, FAKE, x, x + 1024, t, t + 16, W, ws, None) == li.LI_ERR_OVERLAP
+    # gesummv: B NULL, y overlapping B
+    assert lib.li_gesummv(M, N, 1.0, 1.0, FAKE, None, x, t, y, W, ws, None) == li.LI_ERR_NULL_POINTER
+    assert lib.li_gesummv(M, N, 1.0, 1.0, FAKE, FAKE + 2 * ab, x, t, FAKE + 2 * ab + 8, W, ws,
+                          None) == li.LI_ERR_OVERLAP
+    # bicg: r shorter region overlapping s
+    assert lib.li_bicg(M, N, FAKE, x, t, y, t + 8, W, ws, None) == li.LI_ERR_OVERLAP
