@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--rows-only", action="store_true",
                    help="measure only the rows named by --rows (no headline line)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped,forms,paper1024",
+    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped,forms,paper1024,rank,matvec",
                    help="comma list of extra rows to measure")
     return p.parse_args()
 
@@ -263,6 +263,14 @@ def measure_rows(args, torch, li, synth, timer):
             ms = timer.time(fn, reps, 1)
             rows[kind + "_4096x2048"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
                                          "frac_fp32_mfma": round(f / ms / 1e9 / PEAK_FP32_MFMA, 4)}
+            # the same with the centring fused into the contraction's loads
+            if kind == "cov":
+                fn = lambda: li.li_covariance_fused(M, N, X, mean, out, ws)
+            else:
+                fn = lambda: li.li_correlation_fused(M, N, 0.1, X, mean, std, out, ws)
+            ms_f = timer.time(fn, reps, 1)
+            rows[kind + "_fused_4096x2048"] = {"ms": round(ms_f, 4), "GFLOP/s": round(f / ms_f / 1e6, 1),
+                                               "speedup_vs_unfused": round(ms / ms_f, 3)}
         del X, Y, out, ws
 
     if "precision" in want:
@@ -323,7 +331,70 @@ def measure_rows(args, torch, li, synth, timer):
         rows["cov_1024"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1)}
         ms = timer.time(lambda: li.li_correlation(n, n, 0.1, X, Y, mean, std, out, ws), reps, 1)
         rows["corr_1024"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1)}
+
+    if "rank" in want:
+        # 3mm, syrk, syr2k at the paper's size (1024) and at 2048
+        for n in (1024, 2048):
+            m = synth.mm3_inputs(n, n, n, n, n, seed=6)
+            dA, dB, dC, dD = (torch.from_numpy(m[k]).cuda() for k in ("A", "B", "C", "D"))
+            E, F, G = (torch.empty((n, n), device="cuda") for _ in range(3))
+            ms = timer.time(lambda: li.li_mm3(n, n, n, n, n, dA, dB, dC, dD, E, F, G), reps, 1)
+            f = 3 * 2.0 * n ** 3
+            rows["mm3_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
+                                  "frac_fp32_mfma": round(f / ms / 1e9 / PEAK_FP32_MFMA, 4)}
+            r = synth.rank_update_inputs(n, n, seed=7)
+            A, B, C0 = (torch.from_numpy(r[k]).cuda() for k in ("A", "B", "C"))
+            C = C0.clone()
+            ws = torch.empty(li.li_syrk_workspace_bytes(n, n) // 4 + 1, device="cuda")
+            # algorithmic flops: the whole n x n product (2 n^2 k) plus the update
+            f1 = 2.0 * n * n * n + 3.0 * n * n
+            ms = timer.time(lambda: li.li_syrk(n, n, 1.5, A, 1.2, C, ws), reps, 1)
+            rows["syrk_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f1 / ms / 1e6, 1)}
+            f2 = 4.0 * n * n * n + 4.0 * n * n
+            ms = timer.time(lambda: li.li_syr2k(n, n, 1.5, A, B, 1.2, C, ws), reps, 1)
+            rows["syr2k_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f2 / ms / 1e6, 1)}
+            del dA, dB, dC, dD, E, F, G, A, B, C0, C, ws
+
+    if "matvec" in want:
+        rows.update(measure_matvec(torch, li, synth, timer))
     return rows
+
+
+def measure_matvec(torch, li, synth, timer):
+    """atax at 4096, bicg / mvt / gesummv at 16384 (the paper's sizes);
+    HBM-bound: GB/s of algorithmic traffic (each matrix once, each vector
+    read or written once) against the HBM peak."""
+    out = {}
+    c = synth.matvec_inputs(4096, 4096, seed=8)
+    A = torch.from_numpy(c["A"]).cuda()
+    vec = {k: torch.from_numpy(c[k]).cuda() for k in ("x",)}
+    M = N = 4096
+    ws = torch.empty(li.li_matvec_workspace_bytes(M, N) // 4 + 1, device="cuda")
+    t, y = torch.empty(M, device="cuda"), torch.empty(N, device="cuda")
+    ms = timer.time(lambda: li.li_atax(M, N, A, vec["x"], t, y, ws), 30, 1)
+    b = 4.0 * (M * N + 2 * N + M)
+    out["atax_4096"] = {"ms": round(ms, 4), "GB/s": round(b / ms / 1e6, 1),
+                        "frac_hbm": round(b / ms / 1e6 / PEAK_HBM, 4)}
+    del A, ws
+    M = N = 16384
+    c = synth.matvec_inputs(M, N, seed=9, with_b=True)
+    A, B = torch.from_numpy(c["A"]).cuda(), torch.from_numpy(c["B"]).cuda()
+    v = {k: torch.from_numpy(c[k]).cuda() for k in ("x", "p", "r", "y1", "y2", "x1", "x2")}
+    ws = torch.empty(li.li_matvec_workspace_bytes(M, N) // 4 + 1, device="cuda")
+    o1, o2 = torch.empty(M, device="cuda"), torch.empty(N, device="cuda")
+    cases = {
+        "bicg": (lambda: li.li_bicg(M, N, A, v["p"], v["r"], o1, o2, ws), 4.0 * (M * N + 2 * (M + N))),
+        "mvt": (lambda: li.li_mvt(M, N, A, v["y1"], v["y2"], v["x1"], v["x2"], ws),
+                4.0 * (M * N + 3 * (M + N))),
+        "gesummv": (lambda: li.li_gesummv(M, N, 1.5, 1.2, A, B, v["x"], o1, o2, ws),
+                    4.0 * (2 * M * N + N + 2 * M)),
+    }
+    for name, (fn, b) in cases.items():
+        ms = timer.time(fn, 10, 1)
+        out[name + "_16384"] = {"ms": round(ms, 4), "GB/s": round(b / ms / 1e6, 1),
+                                "frac_hbm": round(b / ms / 1e6 / PEAK_HBM, 4)}
+    del A, B, ws
+    return out
 
 
 def measure_grouped(torch, li, synth, timer):

@@ -9,7 +9,8 @@ text (li_tune_save), which li.py loads at import.
 
 Representative problems per bucket (bucket = bit length of max(M, N, K)):
 square GEMMs 256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of
-N = 2 M samples for M = 256 .. 2048, and square reduced-precision GEMMs.
+N = 2 M samples for M = 256 .. 2048, square syrk of order 256 .. 4096 and
+square reduced-precision GEMMs.
 
 Usage: python -m paper_2312_13170_amd.autotune [--out PATH] [--quick]
 """
@@ -65,6 +66,13 @@ def lp_case(n, prec):
     return (n, n, n), lambda: li.li_gemm_ex(n, n, n, 1.0, A, B, 0.0, C, prec, ws)
 
 
+def rank_case(n):
+    A = torch.from_numpy(synth.uniform_pm1(93, "A", (n, n))).cuda()
+    C = torch.from_numpy(synth.uniform_pm1(93, "C", (n, n))).cuda()
+    ws = torch.empty(li.li_syrk_workspace_bytes(n, n) // 4 + 1, device="cuda")
+    return (n, n, n), lambda: li.li_syrk(n, n, 1.5, A, 1.2, C, ws)
+
+
 def search(kernel, cases, reps, log):
     for label, (shape, fn) in cases:
         bucket = li.li_tune_bucket(*shape)
@@ -96,6 +104,8 @@ def main():
     search(li.LI_KERNEL_GEMM_F32, [("gemm %d" % n, gemm_case(n)) for n in gsizes], reps, log)
     ssizes = [512, 2048] if a.quick else [256, 512, 1024, 2048]
     search(li.LI_KERNEL_SYRK_F32, [("cov M=%d" % m, syrk_case(m)) for m in ssizes], reps, log)
+    rsizes = [1024, 2048] if a.quick else [256, 512, 1024, 2048, 4096]
+    search(li.LI_KERNEL_SYRK_ROWS, [("syrk %d" % n, rank_case(n)) for n in rsizes], reps, log)
     lsizes = [2048, 8192] if a.quick else [1024, 2048, 4096, 8192]
     search(li.LI_KERNEL_GEMM_LP, [("bf16x3 %d" % n, lp_case(n, "bf16x3")) for n in lsizes], reps, log)
     li.li_tune_save(a.out)

@@ -335,9 +335,10 @@ size_t li_stats_workspace_bytes(int64_t M, int64_t N) { return li::stats_workspa
 
 namespace {
 
+// fused: no data_out (the centring happens inside the contraction's loads)
 li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float *data,
                        float *data_out, double *mean, double *stdv, float *out, void *ws,
-                       size_t ws_bytes, li_stream stream)
+                       size_t ws_bytes, li_stream stream, bool fused = false)
 {
     li_status s;
     if ((s = li::check_nonneg("M", M)) || (s = li::check_nonneg("N", N))) return s;
@@ -351,7 +352,8 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
     if (M > 0 && ((M + 63) / 64) * ((M + 63) / 64) > (int64_t)0x7fffffff)
         return li::fail(LI_ERR_INVALID_SIZE, "too many output tiles");
     vb = (uint64_t)M * 8;
-    if ((s = li::check_ptr("data", data, xb)) || (s = li::check_ptr("data_out", data_out, xb)) ||
+    const uint64_t yb = fused ? 0 : xb;
+    if ((s = li::check_ptr("data", data, xb)) || (s = li::check_ptr("data_out", data_out, yb)) ||
         (s = li::check_ptr("mean", mean, vb)) ||
         (s = li::check_ptr(corr ? "corr" : "cov", out, sb)))
         return s;
@@ -359,9 +361,9 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
     const size_t need = li::stats_workspace_bytes(M, N);
     if (ws_bytes < need || (need > 0 && ws == nullptr))
         return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-    const Span sX{data, xb}, sY{data_out, xb}, sM{mean, vb}, sS{stdv, corr ? vb : 0}, sO{out, sb},
+    const Span sX{data, xb}, sY{data_out, yb}, sM{mean, vb}, sS{stdv, corr ? vb : 0}, sO{out, sb},
         sW{ws, need};
-    if (data_out != data && (s = li::check_no_overlap("data_out", sY, "data", sX))) return s;
+    if (!fused && data_out != data && (s = li::check_no_overlap("data_out", sY, "data", sX))) return s;
     const Span outs[] = {sM, sS, sO, sW};
     const char *onames[] = {"mean", "stddev", corr ? "corr" : "cov", "workspace"};
     for (int i = 0; i < 4; ++i) {
@@ -372,12 +374,17 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
     }
     if ((s = li::ensure_device())) return s;
     if (M == 0) return LI_OK;
-    if ((s = launched(li::launch_stats(M, N, data, data_out, mean, stdv, corr ? 1 : 0, eps, ws, stream),
+    if ((s = launched(li::launch_stats(M, N, data, data_out, mean, stdv, corr ? 1 : 0, eps, ws, stream,
+                                       fused ? 0 : 1),
                       "column statistics launch")))
         return s;
     const int cfg = li::tune_pick(LI_KERNEL_SYRK_F32, M, M, N);
     const float scale = corr ? 1.0f : (float)(1.0 / (double)(N - 1));
     float *split_ws = (float *)((char *)ws + li::stats_part_bytes(M, N));
+    if (fused)
+        return launched(li::launch_syrk_f32_fused(cfg, M, N, data, mean, li::stats_factor(ws, M, N), out,
+                                                  corr ? 1 : 0, scale, split_ws, stream),
+                        "fused symmetric contraction launch");
     return launched(li::launch_syrk_f32(cfg, M, N, data_out, out, corr ? 1 : 0, scale, split_ws, stream),
                     "symmetric contraction launch");
 }
@@ -522,6 +529,21 @@ li_status li_gesummv(int64_t M, int64_t N, float alpha, float beta, const float 
     if (M < 0 || N < 0) return li::check_nonneg(M < 0 ? "M" : "N", M < 0 ? M : N);
     return matvec_common(li::kMvGesummv, M, N, ins, 3, outs, 2, A, B, x, nullptr, tmp, y, alpha, beta,
                          workspace, workspace_bytes, zo, zl, 2, stream);
+}
+
+li_status li_covariance_fused(int64_t M, int64_t N, const float *data, double *mean, float *cov,
+                              void *workspace, size_t workspace_bytes, li_stream stream)
+{
+    return stats_common(false, M, N, 0.0, data, nullptr, mean, nullptr, cov, workspace,
+                        workspace_bytes, stream, true);
+}
+
+li_status li_correlation_fused(int64_t M, int64_t N, double eps, const float *data, double *mean,
+                               double *stddev, float *corr, void *workspace,
+                               size_t workspace_bytes, li_stream stream)
+{
+    return stats_common(true, M, N, eps, data, nullptr, mean, stddev, corr, workspace,
+                        workspace_bytes, stream, true);
 }
 
 li_status li_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, li_precision p,

@@ -1,0 +1,44 @@
+// Covariance / correlation with the centring fused into the contraction
+// (kernel fusion, named as future work in the paper's conclusion): the
+// symmetric contraction reads the raw data and centres (or normalises) each
+// element on its way into LDS with the FP64 column statistics, so the
+// centred matrix never goes through HBM.  The transform is the one the
+// separate centring kernel applies, element by element, so the results are
+// bitwise those of the unfused path for the same tile shape.
+#include <hip/hip_runtime.h>
+
+#include "f32_tile.h"
+#include "li_internal.h"
+#include "symm_kernels.h"
+#include "tiles.h"
+
+namespace li {
+
+int launch_syrk_f32_fused(int cfg, int64_t M, int64_t N, const float *X, const double *mean,
+                          const double *factor, float *S, int mode, float scale, float *split_ws,
+                          void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    const bool v4 = (M % 4 == 0 && ((uintptr_t)X & 15) == 0);
+    const SymArgs a{X, nullptr, M, M, N, S, mode, scale, 0.f, 1, mean, factor};
+    // direct-to-LDS candidates (PF 4) have no register stage to transform
+    // in; they run with the pipelined register path (PF 3) instead
+#define LI_T(BM, BN, BK, WM, WN, LOAD, PF, XF) \
+    F32Tile<BM, BN, BK, WM, WN, true, LOAD, (PF == 4 ? 3 : PF), false, XF>
+#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                        \
+    case IDX:                                                                                         \
+        if (mode == 1)                                                                                \
+            return v4 ? run_sym<LI_T(BM, BN, BK, WM, WN, kLoadVec4, PF, 2), kSymCols>(a, SK, split_ws, s) \
+                      : run_sym<LI_T(BM, BN, BK, WM, WN, kLoadScalar, PF, 2), kSymCols>(a, SK, split_ws, s); \
+        return v4 ? run_sym<LI_T(BM, BN, BK, WM, WN, kLoadVec4, PF, 1), kSymCols>(a, SK, split_ws, s)     \
+                  : run_sym<LI_T(BM, BN, BK, WM, WN, kLoadScalar, PF, 1), kSymCols>(a, SK, split_ws, s);
+    switch (cfg) {
+        LI_SYRK_F32_CANDIDATES(LI_CASE)
+    default:
+        return (int)hipErrorInvalidValue;
+    }
+#undef LI_CASE
+#undef LI_T
+}
+
+}  // namespace li

@@ -72,13 +72,16 @@ struct TileLoader {
     static_assert(TC % 4 == 0, "tile width must be a multiple of 4");
     static_assert(NCH % NT == 0, "tile chunks must divide evenly among threads");
     static constexpr int PER = NCH / NT;
+    static_assert(PER * 4 <= 64, "validity mask holds 64 elements");
     f32x4 v[PER];
+    uint64_t okm;  // bit 4 i + e: element e of chunk i lies inside the matrix
 
     __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
                                          int64_t cols, int64_t r0, int64_t c0, int tid,
                                          bool dyn_vec4)
     {
         const bool vec4 = MODE == kLoadVec4 || (MODE == kLoadDynamic && dyn_vec4);
+        okm = 0;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int c = tid + i * NT;
@@ -89,6 +92,7 @@ struct TileLoader {
                 const bool ok = rok && gc < cols;
                 const f32x4 x = *reinterpret_cast<const f32x4 *>(p + (ok ? gr * ld + gc : 0));
                 v[i] = ok ? x : f32x4{0.f, 0.f, 0.f, 0.f};
+                okm |= (ok ? (uint64_t)15 : (uint64_t)0) << (4 * i);
             } else {
                 const int64_t base = gr * ld + gc;
 #pragma unroll
@@ -96,8 +100,34 @@ struct TileLoader {
                     const bool ok = rok && gc + e < cols;
                     const float x = p[ok ? base + e : 0];
                     v[i][e] = ok ? x : 0.f;
+                    okm |= (ok ? (uint64_t)1 : (uint64_t)0) << (4 * i + e);
                 }
             }
+        }
+    }
+
+    // Store with the centring transform of the statistics kernels applied
+    // to in-matrix elements: y = fl32(((double)x - mean[e]) * factor[e])
+    // (without the product when SCALE is false); out-of-matrix elements stay
+    // 0.  Requires every chunk of a thread to lie in the same four columns
+    // (NT a multiple of the chunks per row), whose mean / factor are given.
+    template <int LDL, bool SCALE>
+    __device__ __forceinline__ void store_centred(float *lds, int tid, const double (&mean)[4],
+                                                  const double (&factor)[4]) const
+    {
+        static_assert(NT % CPR == 0, "each thread must keep its columns");
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = tid + i * NT;
+            const int r = c / CPR, cc = (c % CPR) * 4;
+            f32x4 y;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                double d = (double)v[i][e] - mean[e];
+                if (SCALE) d *= factor[e];
+                y[e] = ((okm >> (4 * i + e)) & 1) ? (float)d : 0.f;
+            }
+            *reinterpret_cast<f32x4 *>(lds + r * LDL + cc) = y;
         }
     }
 
@@ -124,9 +154,15 @@ struct TileLoader {
 // next two, with LDS operand reads pipelined across the barrier; 4: direct
 // HBM-to-LDS loads into a three-stage ring, vector loads only).
 template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1,
-          bool B_NMAJOR = false>
+          bool B_NMAJOR = false, int XFORM_ = 0>
 struct F32Tile {
     static_assert(PF >= 1 && PF <= 4, "prefetch mode is 1 to 4");
+    // XFORM: 0 operands used as loaded; 1 / 2: both k-major operands are
+    // raw data, centred (1) or normalised (2) column by column on their way
+    // into LDS (the statistics kernels' transform, fused into the loads).
+    static constexpr int XFORM = XFORM_;
+    static_assert(XFORM == 0 || (A_KMAJOR && !B_NMAJOR && PF != 4),
+                  "fused centring needs k-major operands loaded through registers");
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
@@ -147,6 +183,45 @@ struct F32Tile {
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
     using BLoader = TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>;
+
+    // Per-thread column statistics for XFORM: the four columns of A (m) and
+    // of B (n) that this thread's chunks cover.
+    struct XRegs {
+        double ma[4], fa[4], mb[4], fb[4];
+    };
+
+    __device__ __forceinline__ static void load_xregs(XRegs &x, const double *mean,
+                                                      const double *factor, int64_t M, int64_t N,
+                                                      int64_t m0, int64_t n0)
+    {
+        const int tid = threadIdx.x;
+        const int64_t ca = m0 + (tid % ALoader::CPR) * 4, cb = n0 + (tid % BLoader::CPR) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            x.ma[e] = ca + e < M ? mean[ca + e] : 0.0;
+            x.mb[e] = cb + e < N ? mean[cb + e] : 0.0;
+            x.fa[e] = XFORM == 2 && ca + e < M ? factor[ca + e] : 0.0;
+            x.fb[e] = XFORM == 2 && cb + e < N ? factor[cb + e] : 0.0;
+        }
+    }
+
+    __device__ __forceinline__ static void store_a(const ALoader &la, float *As, int tid,
+                                                   const XRegs *x)
+    {
+        if constexpr (XFORM != 0)
+            la.template store_centred<A_LD, XFORM == 2>(As, tid, x->ma, x->fa);
+        else
+            la.template store<A_LD>(As, tid);
+    }
+
+    __device__ __forceinline__ static void store_b(const BLoader &lb, float *Bs, int tid,
+                                                   const XRegs *x)
+    {
+        if constexpr (XFORM != 0)
+            lb.template store_centred<B_LD, XFORM == 2>(Bs, tid, x->mb, x->fb);
+        else
+            lb.template store<B_LD>(Bs, tid);
+    }
 
     __device__ __forceinline__ static void zero(f32x16 (&acc)[TM][TN])
     {
@@ -290,7 +365,7 @@ struct F32Tile {
     __device__ __forceinline__ static void mainloop_pipelined(
         float *As, float *Bs, ALoader &la, BLoader &lb, const float *A, int64_t lda, const float *B,
         int64_t ldb, int64_t M, int64_t N, int64_t kbeg, int64_t kend, int64_t m0, int64_t n0,
-        int64_t nk, f32x16 (&acc)[TM][TN], bool v4)
+        int64_t nk, f32x16 (&acc)[TM][TN], bool v4, const XRegs *xr)
     {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
@@ -308,8 +383,8 @@ struct F32Tile {
             load_a(la, A, lda, M, kend, m0, k2, tid, v4);
             load_b(lb, B, ldb, N, kend, n0, k2, tid, v4);
             kloop(As, Bs, f, acc, wm0, wn0, lane);
-            la1.template store<A_LD>(As + A_STAGE, tid);
-            lb1.template store<B_LD>(Bs + B_STAGE, tid);
+            store_a(la1, As + A_STAGE, tid, xr);
+            store_b(lb1, Bs + B_STAGE, tid, xr);
             __syncthreads();
             {
                 Frag g;
@@ -321,8 +396,8 @@ struct F32Tile {
             load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4);
             kloop(As + A_STAGE, Bs + B_STAGE, f, acc, wm0, wn0, lane);
             if (kt + 2 < nk) {
-                la.template store<A_LD>(As, tid);
-                lb.template store<B_LD>(Bs, tid);
+                store_a(la, As, tid, xr);
+                store_b(lb, Bs, tid, xr);
                 __syncthreads();
                 Frag g;
                 read_frag(As, Bs, 0, wm0, wn0, lane, g);
@@ -543,7 +618,7 @@ struct F32Tile {
                                                     const float *B, int64_t ldb, int64_t M,
                                                     int64_t N, int64_t kbeg, int64_t kend,
                                                     int64_t m0, int64_t n0, f32x16 (&acc)[TM][TN],
-                                                    bool v4 = true)
+                                                    bool v4 = true, const XRegs *xr = nullptr)
     {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
@@ -561,10 +636,10 @@ struct F32Tile {
         BLoader lb;
         load_a(la, A, lda, M, kend, m0, kbeg, tid, v4);
         load_b(lb, B, ldb, N, kend, n0, kbeg, tid, v4);
-        la.template store<A_LD>(As, tid);
-        lb.template store<B_LD>(Bs, tid);
+        store_a(la, As, tid, xr);
+        store_b(lb, Bs, tid, xr);
         if (PF == 3) {
-            mainloop_pipelined(As, Bs, la, lb, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc, v4);
+            mainloop_pipelined(As, Bs, la, lb, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc, v4, xr);
             return;
         }
         if (PF == 2) {
@@ -585,15 +660,15 @@ struct F32Tile {
                 load_a(la, A, lda, M, kend, m0, k2, tid, v4);
                 load_b(lb, B, ldb, N, kend, n0, k2, tid, v4);
                 compute(As, Bs, acc, wm0, wn0, lane);
-                la1.template store<A_LD>(As + A_STAGE, tid);
-                lb1.template store<B_LD>(Bs + B_STAGE, tid);
+                store_a(la1, As + A_STAGE, tid, xr);
+                store_b(lb1, Bs + B_STAGE, tid, xr);
                 __syncthreads();
                 load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
                 load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4);
                 compute(As + A_STAGE, Bs + B_STAGE, acc, wm0, wn0, lane);
                 if (kt + 2 < nk) {
-                    la.template store<A_LD>(As, tid);
-                    lb.template store<B_LD>(Bs, tid);
+                    store_a(la, As, tid, xr);
+                    store_b(lb, Bs, tid, xr);
                 }
                 __syncthreads();
             }
@@ -614,8 +689,8 @@ struct F32Tile {
             }
             compute(As + cur * A_STAGE, Bs + cur * B_STAGE, acc, wm0, wn0, lane);
             if (more) {
-                la.template store<A_LD>(As + (cur ^ 1) * A_STAGE, tid);
-                lb.template store<B_LD>(Bs + (cur ^ 1) * B_STAGE, tid);
+                store_a(la, As + (cur ^ 1) * A_STAGE, tid, xr);
+                store_b(lb, Bs + (cur ^ 1) * B_STAGE, tid, xr);
             }
             __syncthreads();
         }

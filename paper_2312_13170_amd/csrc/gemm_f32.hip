@@ -83,7 +83,7 @@ int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int
 {
     hipStream_t s = (hipStream_t)stream;
     const bool v4 = (M % 4 == 0 && aligned16(Y));
-    const SymArgs a{Y, nullptr, M, M, N, S, mode, scale, 0.f, 1};
+    const SymArgs a{Y, nullptr, M, M, N, S, mode, scale, 0.f, 1, nullptr, nullptr};
     switch (cfg) {
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                      \
     case IDX:                                                                                       \

@@ -61,6 +61,13 @@ size_t syrk_split_bytes(int64_t M);
 int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode,
                     float scale, float *split_ws, void *stream);
 
+// The same contraction on the raw data X (N x M) with the centring fused
+// into the operand loads (cov_fused.hip): mean and, for mode 1, the
+// normalisation factors of launch_stats.
+int launch_syrk_f32_fused(int cfg, int64_t M, int64_t N, const float *X, const double *mean,
+                          const double *factor, float *S, int mode, float scale, float *split_ws,
+                          void *stream);
+
 // Row-form symmetric updates (symm_rows.hip): C = alpha*P + beta*C with
 // P = A A^T (B == NULL) or A B^T + B A^T; A, B n x k, C n x n.  Candidates
 // with split_k > 1 need split_ws of sym_rows_split_bytes(n) bytes.
@@ -79,8 +86,12 @@ struct StatsPlan {
 StatsPlan stats_plan(int64_t M, int64_t N);
 size_t stats_part_bytes(int64_t M, int64_t N);      // statistics part of the workspace
 size_t stats_workspace_bytes(int64_t M, int64_t N);  // statistics + contraction split
+// centre == 0: only the statistics (mean, stdv and the factors kept in the
+// workspace, see stats_factor); Y is then not written.
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
-                 int correlation, double eps, void *ws, void *stream);
+                 int correlation, double eps, void *ws, void *stream, int centre = 1);
+// the per-column normalisation factors inside the statistics workspace
+const double *stats_factor(const void *ws, int64_t M, int64_t N);
 
 // Matrix-vector kernels (matvec.hip), A (and B) M x N, M, N >= 1:
 //   kMvAtax    v1 = x; o1 = tmp = A x; o2 = y = A^T tmp

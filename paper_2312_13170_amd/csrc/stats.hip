@@ -152,8 +152,14 @@ size_t stats_workspace_bytes(int64_t M, int64_t N)
     return stats_part_bytes(M, N) + syrk_split_bytes(M);
 }
 
+const double *stats_factor(const void *ws, int64_t M, int64_t N)
+{
+    StatsPlan p = stats_plan(M, N);
+    return (const double *)ws + p.nsplit * 2 * M;
+}
+
 int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, double *stdv,
-                 int correlation, double eps, void *ws, void *stream)
+                 int correlation, double eps, void *ws, void *stream, int centre)
 {
     hipStream_t s = (hipStream_t)stream;
     StatsPlan p = stats_plan(M, N);
@@ -168,6 +174,7 @@ int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, d
                        p.nsplit, p.rows_per_split, N, M, correlation, eps, mean, stdv, factor);
     e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
+    if (!centre) return 0;
     const bool v4 = (M % 4 == 0) && (((uintptr_t)X & 15) == 0) && (((uintptr_t)Y & 15) == 0);
     const int64_t work = v4 ? N * M / 4 : N * M;
     int64_t blocks = (work + 255) / 256;

@@ -5,6 +5,8 @@
 // operand forms share the kernels:
 //   kSymCols : S = Y^T Y, Y (kdim x n) row-major; both operands k-major
 //              (covariance / correlation after centring; T has A_KMAJOR).
+//              With T::XFORM the operand is the raw data and the centring
+//              happens in the loads (the fused statistics kernels).
 //   kSymRows : P = X X^T, X (n x kdim) row-major; both operands have k
 //              contiguous (syrk; T has B_NMAJOR).
 //   kSymRows2: P = X Z^T + Z X^T, X and Z (n x kdim) row-major (syr2k): the
@@ -32,6 +34,8 @@ struct SymArgs {
     float scale;     // mode 0: multiplier; mode 2: alpha
     float beta;      // mode 2 only
     int reads;       // 0: operands are not read (alpha == 0), result = beta*S
+    const double *mean;    // tiles with XFORM: column means of the raw data X
+    const double *factor;  // and, for XFORM 2, the normalisation factors
 };
 
 template <class T, int FORM>
@@ -39,6 +43,12 @@ __device__ __forceinline__ void sym_reduce(float *lds, const SymArgs &a, int64_t
                                            int64_t kend, int64_t m0, int64_t n0,
                                            f32x16 (&acc)[T::TM][T::TN])
 {
+    if constexpr (T::XFORM != 0) {
+        typename T::XRegs xr;
+        T::load_xregs(xr, a.mean, a.factor, a.n, a.n, m0, n0);
+        T::mainloop(lds, a.X, a.ld, a.X, a.ld, a.n, a.n, kbeg, kend, m0, n0, acc, true, &xr);
+        return;
+    }
     T::mainloop(lds, a.X, a.ld, FORM == kSymRows2 ? a.Z : a.X, a.ld, a.n, a.n, kbeg, kend, m0, n0,
                 acc);
     if (FORM == kSymRows2) T::mainloop(lds, a.Z, a.ld, a.X, a.ld, a.n, a.n, kbeg, kend, m0, n0, acc);

@@ -26,7 +26,7 @@ int launch_sym_rows(int cfg, int64_t n, int64_t k, float alpha, const float *A, 
     hipStream_t s = (hipStream_t)stream;
     const bool two = B != nullptr;
     const bool v4 = k % 4 == 0 && ((uintptr_t)A & 15) == 0 && (!two || ((uintptr_t)B & 15) == 0);
-    const SymArgs a{A, B, k, n, k, C, 2, alpha, beta, alpha != 0.f && k > 0 ? 1 : 0};
+    const SymArgs a{A, B, k, n, k, C, 2, alpha, beta, alpha != 0.f && k > 0 ? 1 : 0, nullptr, nullptr};
     switch (cfg) {
 #define LI_RUN(BM, BN, BK, WM, WN, SK, LOAD, PF, FORM) \
     run_sym<F32Tile<BM, BN, BK, WM, WN, false, LOAD, PF, true>, FORM>(a, SK, split_ws, s)

@@ -26,7 +26,7 @@ import sqlite3
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/f32_tile.h", "csrc/gemm_f32.hip", "csrc/tiles.h", "csrc/stats.hip",
                   "csrc/stats_dev.h", "csrc/gemm_lp.hip", "csrc/grouped.hip", "csrc/symm_kernels.h",
-                  "csrc/symm_rows.hip", "csrc/matvec.hip", "tune_gfx950.txt"]
+                  "csrc/symm_rows.hip", "csrc/matvec.hip", "csrc/cov_fused.hip", "tune_gfx950.txt"]
 
 
 def source_hash(files=KERNEL_SOURCES):
@@ -63,7 +63,7 @@ def still_current(text):
         return False
 
 
-def short(name, n=96):
+def short(name, n=150):
     return name if len(name) <= n else name[: n - 3] + "..."
 
 

@@ -247,3 +247,16 @@ def test_matvec_argument_rules(li):
                           None) == li.LI_ERR_OVERLAP
     # bicg: r shorter region overlapping s
     assert lib.li_bicg(M, N, FAKE, x, t, y, t + 8, W, ws, None) == li.LI_ERR_OVERLAP
+
+
+def test_fused_statistics_argument_rules(li):
+    lib = li._lib
+    M, N = 8, 16
+    xb = 4 * M * N
+    ws = lib.li_stats_workspace_bytes(M, N)
+    # no data_out: the only outputs are mean, (stddev,) cov / corr
+    assert lib.li_covariance_fused(M, 1, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 4 * xb, ws, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_covariance_fused(M, N, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 4 * xb, ws - 8, None) == li.LI_ERR_WORKSPACE
+    assert lib.li_covariance_fused(M, N, FAKE, FAKE + 8, FAKE + 2 * xb, FAKE + 4 * xb, ws, None) == li.LI_ERR_OVERLAP
+    assert lib.li_correlation_fused(M, N, 0.1, FAKE, FAKE + xb, None, FAKE + 2 * xb, FAKE + 4 * xb, ws,
+                                    None) == li.LI_ERR_NULL_POINTER

@@ -135,3 +135,78 @@ def test_config2_full_size_sampled(li, orc):
         scale = np.max(np.abs(np.diag(out))) if not corr else 1.0
         assert np.max(np.abs(got - ref)) / scale < TOL_FP32
         assert np.array_equal(out, out.T)
+
+
+# ------------------------------------------------ centring fused into the contraction
+def run_fused(li, X, corr, eps=0.1):
+    N, M = X.shape
+    dX = dev(X)
+    mean = empty((M,), torch.float64, fill=float("nan"))
+    std = empty((M,), torch.float64, fill=float("nan")) if corr else None
+    out = empty((M, M), fill=float("nan"))
+    ws = empty((li.li_stats_workspace_bytes(M, N) // 8 + 1,), torch.float64)
+    if corr:
+        li.li_correlation_fused(M, N, eps, dX, mean, std, out, ws)
+    else:
+        li.li_covariance_fused(M, N, dX, mean, out, ws)
+    assert np.array_equal(host(dX), X)  # the data is only read
+    return host(mean), (host(std) if corr else None), host(out)
+
+
+@pytest.mark.parametrize("N,M", [(2, 1), (37, 5), (300, 129), (513, 600), (1000, 250)])
+def test_fused_equals_unfused_bitwise(li, orc, N, M):
+    # the fused loads apply the centring kernel's arithmetic element by
+    # element, so every result is bitwise that of the two-kernel path
+    say("fused stats", N, M)
+    X = synth.stats_inputs(N, M, seed=45)["data"]
+    if M > 3:
+        X[:, 3] = 0.05 * X[:, 3]
+    for corr in (False, True):
+        _, mean, std, out = run_stats(li, X, corr=corr)
+        fmean, fstd, fout = run_fused(li, X, corr=corr)
+        assert np.array_equal(mean, fmean)
+        assert np.array_equal(out, fout), corr
+        if corr:
+            assert np.array_equal(std, fstd)
+    _, _, rcov = orc.covariance(X, want_y=False)
+    assert normwise(run_fused(li, X, False)[2], rcov) < TOL_FP32
+
+
+def test_fused_every_tile_shape(li, orc):
+    N, M = 333, 300
+    X = synth.stats_inputs(N, M, seed=46)["data"]
+    _, _, _, rcorr = orc.correlation(X, want_y=False)
+    try:
+        for cfg in range(li.li_tune_num_candidates(li.LI_KERNEL_SYRK_F32)):
+            say("fused correlation candidate", cfg)
+            li.li_tune_force(li.LI_KERNEL_SYRK_F32, cfg)
+            _, _, _, corr = run_stats(li, X, corr=True)
+            _, _, fcorr = run_fused(li, X, corr=True)
+            assert np.array_equal(corr, fcorr), cfg
+            assert normwise(fcorr, rcorr) < TOL_FP32, cfg
+    finally:
+        li.li_tune_force(li.LI_KERNEL_SYRK_F32, -1)
+
+
+def test_fused_constant_columns(li):
+    say("fused stats constant columns")
+    N, M = 200, 70
+    X = synth.stats_inputs(N, M, seed=47)["data"]
+    consts = {0: 3.25, 17: -1024.5, 69: 1000.0}
+    for j, c in consts.items():
+        X[:, j] = c
+    _, _, cov = run_fused(li, X, corr=False)
+    _, std, corr = run_fused(li, X, corr=True)
+    for j in consts:
+        assert np.all(cov[j, :] == 0.0) and np.all(cov[:, j] == 0.0)
+        assert std[j] == 1.0 and corr[j, j] == 1.0
+        assert np.all(np.delete(corr[j, :], j) == 0.0)
+
+
+def test_fused_config2_bitwise(li):
+    say("fused stats 4096 x 2048")
+    X = synth.config(2)["data"]
+    for corr in (False, True):
+        _, mean, std, out = run_stats(li, X, corr=corr)
+        fmean, fstd, fout = run_fused(li, X, corr=corr)
+        assert np.array_equal(out, fout) and np.array_equal(mean, fmean)
