@@ -346,13 +346,17 @@ def measure_rows(args, torch, li, synth, timer):
             A, B, C0 = (torch.from_numpy(r[k]).cuda() for k in ("A", "B", "C"))
             C = C0.clone()
             ws = torch.empty(li.li_syrk_workspace_bytes(n, n) // 4 + 1, device="cuda")
-            # algorithmic flops: the whole n x n product (2 n^2 k) plus the update
-            f1 = 2.0 * n * n * n + 3.0 * n * n
+            # flops of the symmetric product counted once per unordered pair
+            # (n (n + 1) / 2 dot products of length k; syr2k two of them),
+            # plus the update of all n^2 elements
+            f1 = float(n) * (n + 1) * n + 3.0 * n * n
             ms = timer.time(lambda: li.li_syrk(n, n, 1.5, A, 1.2, C, ws), reps, 1)
-            rows["syrk_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f1 / ms / 1e6, 1)}
-            f2 = 4.0 * n * n * n + 4.0 * n * n
+            rows["syrk_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f1 / ms / 1e6, 1),
+                                   "frac_fp32_mfma": round(f1 / ms / 1e9 / PEAK_FP32_MFMA, 4)}
+            f2 = 2.0 * n * (n + 1) * n + 4.0 * n * n
             ms = timer.time(lambda: li.li_syr2k(n, n, 1.5, A, B, 1.2, C, ws), reps, 1)
-            rows["syr2k_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f2 / ms / 1e6, 1)}
+            rows["syr2k_%d" % n] = {"ms": round(ms, 4), "GFLOP/s": round(f2 / ms / 1e6, 1),
+                                    "frac_fp32_mfma": round(f2 / ms / 1e9 / PEAK_FP32_MFMA, 4)}
             del dA, dB, dC, dD, E, F, G, A, B, C0, C, ws
 
     if "matvec" in want:

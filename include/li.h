@@ -147,12 +147,12 @@ li_status li_correlation(int64_t M, int64_t N, double eps, const float *data,
                          void *workspace, size_t workspace_bytes, li_stream stream);
 
 /* Covariance and correlation with the centring fused into the contraction
- * (kernel fusion, the future work of the paper's conclusion): the symmetric
- * contraction reads `data` and centres (or normalises) every element on its
- * way into LDS, so the centred N x M matrix is neither written nor read
- * back.  Same arguments, rules, workspace and results (mean, stddev, cov /
- * corr, bitwise for the same tile shape) as li_covariance / li_correlation,
- * without data_out. */
+ * (the kernel fusion of Sec. VII-B, which keeps dataflow between kernels out
+ * of global memory): the symmetric contraction reads `data` and centres (or
+ * normalises) every element on its way into LDS, so the centred N x M
+ * matrix is neither written nor read back.  Same arguments, rules,
+ * workspace and results (mean, stddev, cov / corr, bitwise for the same tile
+ * shape) as li_covariance / li_correlation, without data_out. */
 li_status li_covariance_fused(int64_t M, int64_t N, const float *data, double *mean, float *cov,
                               void *workspace, size_t workspace_bytes, li_stream stream);
 li_status li_correlation_fused(int64_t M, int64_t N, double eps, const float *data,

@@ -1,10 +1,11 @@
 // Covariance / correlation with the centring fused into the contraction
-// (kernel fusion, named as future work in the paper's conclusion): the
-// symmetric contraction reads the raw data and centres (or normalises) each
-// element on its way into LDS with the FP64 column statistics, so the
-// centred matrix never goes through HBM.  The transform is the one the
-// separate centring kernel applies, element by element, so the results are
-// bitwise those of the unfused path for the same tile shape.
+// (the kernel fusion of Sec. VII-B, which keeps dataflow between kernels out
+// of global memory): the symmetric contraction reads the raw data and
+// centres (or normalises) each element on its way into LDS with the FP64
+// column statistics, so the centred matrix never goes through HBM.  The
+// transform is the one the separate centring kernel applies, element by
+// element, so the results are bitwise those of the unfused path for the
+// same tile shape.
 #include <hip/hip_runtime.h>
 
 #include "f32_tile.h"
