@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--rows-only", action="store_true",
                    help="measure only the rows named by --rows (no headline line)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped,forms,paper1024,rank,matvec",
+    p.add_argument("--rows", default="gemm256,cov,corr,precision,grouped,forms,paper1024,rank,matvec,vendor",
                    help="comma list of extra rows to measure")
     return p.parse_args()
 
@@ -361,6 +361,23 @@ def measure_rows(args, torch, li, synth, timer):
 
     if "matvec" in want:
         rows.update(measure_matvec(torch, li, synth, timer))
+
+    if "vendor" in want:
+        # context only: the vendor BLAS behind torch.mm (FP32, no TF32) on
+        # the headline GEMM shape, next to li_gemm on the same operands
+        n = 2048
+        torch.backends.cuda.matmul.allow_tf32 = False
+        c = synth.gemm_inputs(n, n, n, seed=2)
+        A, B = torch.from_numpy(c["A"]).cuda(), torch.from_numpy(c["B"]).cuda()
+        C = torch.empty((n, n), device="cuda")
+        ms_v = timer.time(lambda: torch.mm(A, B, out=C), reps, 2)
+        ms_l = timer.time(lambda: li.li_gemm(n, n, n, 1.0, A, B, 0.0, C), reps, 2)
+        f = 2.0 * n ** 3
+        rows["vendor_sgemm_2048"] = {"torch_mm_ms": round(ms_v, 4),
+                                     "torch_mm_TFLOP/s": round(f / ms_v / 1e9, 1),
+                                     "li_gemm_ms": round(ms_l, 4),
+                                     "li_gemm_TFLOP/s": round(f / ms_l / 1e9, 1)}
+        del A, B, C
     return rows
 
 

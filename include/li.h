@@ -150,9 +150,13 @@ li_status li_correlation(int64_t M, int64_t N, double eps, const float *data,
  * (the kernel fusion of Sec. VII-B, which keeps dataflow between kernels out
  * of global memory): the symmetric contraction reads `data` and centres (or
  * normalises) every element on its way into LDS, so the centred N x M
- * matrix is neither written nor read back.  Same arguments, rules,
- * workspace and results (mean, stddev, cov / corr, bitwise for the same tile
- * shape) as li_covariance / li_correlation, without data_out. */
+ * matrix is neither written nor read back.  Same arguments, rules and
+ * workspace as li_covariance / li_correlation, without data_out; mean and
+ * stddev are bitwise the same.  Inside the contraction each element is
+ * centred in FP32 with the mean rounded to FP32, which shifts a column's
+ * centred values by the same amount; that changes the result by about
+ * N d_a d_b (d <= 2^-24 |mean|), far below its FP32 rounding, so cov / corr
+ * agree with the unfused results to a few units in the last place. */
 li_status li_covariance_fused(int64_t M, int64_t N, const float *data, double *mean, float *cov,
                               void *workspace, size_t workspace_bytes, li_stream stream);
 li_status li_correlation_fused(int64_t M, int64_t N, double eps, const float *data,
@@ -272,7 +276,8 @@ enum { LI_KERNEL_GEMM_F32 = 0, LI_KERNEL_SYRK_F32 = 1, LI_KERNEL_GEMM_LP = 2, LI
 typedef struct li_tile_config {
     int32_t bm, bn, bk;     /* block tile and K-tile                    */
     int32_t waves_m, waves_n;
-    int32_t split_k;        /* reduction split (1 = none)               */
+    int32_t split_k;        /* reduction split (1 = none; 0 = stream-K:
+                               balanced ranges of (tile, K-tile) work)  */
     int32_t prefetch;       /* main-loop mode 1-4 (1, 2: K-tiles in flight
                                from HBM; 3: 2 plus operand reads pipelined
                                across the barrier; 4: direct HBM-to-LDS

@@ -1,11 +1,12 @@
 // Covariance / correlation with the centring fused into the contraction
 // (the kernel fusion of Sec. VII-B, which keeps dataflow between kernels out
 // of global memory): the symmetric contraction reads the raw data and
-// centres (or normalises) each element on its way into LDS with the FP64
-// column statistics, so the centred matrix never goes through HBM.  The
-// transform is the one the separate centring kernel applies, element by
-// element, so the results are bitwise those of the unfused path for the
-// same tile shape.
+// centres (or normalises) each element on its way into LDS, so the centred
+// matrix never goes through HBM.  Each element is loaded by every tile of
+// its block row and column, so the transform is repeated that many times
+// and has to be cheap: one FP32 subtraction of the mean rounded to FP32
+// (and one product for correlation), see F32Tile::store_centred and XRegs.
+// The statistics themselves (mean, stddev) are those of the FP64 kernels.
 #include <hip/hip_runtime.h>
 
 #include "f32_tile.h"

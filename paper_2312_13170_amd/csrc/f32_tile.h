@@ -72,16 +72,15 @@ struct TileLoader {
     static_assert(TC % 4 == 0, "tile width must be a multiple of 4");
     static_assert(NCH % NT == 0, "tile chunks must divide evenly among threads");
     static constexpr int PER = NCH / NT;
-    static_assert(PER * 4 <= 64, "validity mask holds 64 elements");
     f32x4 v[PER];
-    uint64_t okm;  // bit 4 i + e: element e of chunk i lies inside the matrix
 
+    // Elements outside the matrix take the value `fill` (per column of the
+    // chunk; zeros unless a transform at the store maps fill to zero).
     __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
                                          int64_t cols, int64_t r0, int64_t c0, int tid,
-                                         bool dyn_vec4)
+                                         bool dyn_vec4, f32x4 fill = f32x4{0.f, 0.f, 0.f, 0.f})
     {
         const bool vec4 = MODE == kLoadVec4 || (MODE == kLoadDynamic && dyn_vec4);
-        okm = 0;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int c = tid + i * NT;
@@ -91,29 +90,26 @@ struct TileLoader {
             if (vec4) {
                 const bool ok = rok && gc < cols;
                 const f32x4 x = *reinterpret_cast<const f32x4 *>(p + (ok ? gr * ld + gc : 0));
-                v[i] = ok ? x : f32x4{0.f, 0.f, 0.f, 0.f};
-                okm |= (ok ? (uint64_t)15 : (uint64_t)0) << (4 * i);
+                v[i] = ok ? x : fill;
             } else {
                 const int64_t base = gr * ld + gc;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const bool ok = rok && gc + e < cols;
                     const float x = p[ok ? base + e : 0];
-                    v[i][e] = ok ? x : 0.f;
-                    okm |= (ok ? (uint64_t)1 : (uint64_t)0) << (4 * i + e);
+                    v[i][e] = ok ? x : fill[e];
                 }
             }
         }
     }
 
-    // Store with the centring transform of the statistics kernels applied
-    // to in-matrix elements: y = fl32(((double)x - mean[e]) * factor[e])
-    // (without the product when SCALE is false); out-of-matrix elements stay
-    // 0.  Requires every chunk of a thread to lie in the same four columns
-    // (NT a multiple of the chunks per row), whose mean / factor are given.
+    // Store with a column centring applied: y = x - m[e] (then y *= f[e]
+    // when SCALE), in FP32, with m the column mean rounded to FP32.  Loads
+    // fill out-of-matrix elements with m, so they become exactly 0.
+    // Requires every chunk of a thread to lie in the same four columns (NT a
+    // multiple of the chunks per row).
     template <int LDL, bool SCALE>
-    __device__ __forceinline__ void store_centred(float *lds, int tid, const double (&mean)[4],
-                                                  const double (&factor)[4]) const
+    __device__ __forceinline__ void store_centred(float *lds, int tid, f32x4 m, f32x4 f) const
     {
         static_assert(NT % CPR == 0, "each thread must keep its columns");
 #pragma unroll
@@ -123,9 +119,8 @@ struct TileLoader {
             f32x4 y;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                double d = (double)v[i][e] - mean[e];
-                if (SCALE) d *= factor[e];
-                y[e] = ((okm >> (4 * i + e)) & 1) ? (float)d : 0.f;
+                y[e] = v[i][e] - m[e];
+                if (SCALE) y[e] *= f[e];
             }
             *reinterpret_cast<f32x4 *>(lds + r * LDL + cc) = y;
         }
@@ -185,9 +180,16 @@ struct F32Tile {
     using BLoader = TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>;
 
     // Per-thread column statistics for XFORM: the four columns of A (m) and
-    // of B (n) that this thread's chunks cover.
+    // of B (n) that this thread's chunks cover, mean rounded to FP32 and
+    // normalisation factor.
+    //
+    // Centring with the rounded mean m = mean + d shifts every centred value
+    // of a column by the same d (|d| <= 2^-24 |mean|); the products then gain
+    // d_a sum_i y_ib + d_b sum_i y_ia + n d_a d_b, where the sums of centred
+    // values vanish, so the contraction changes by about n d_a d_b:
+    // far below FP32 rounding of the result.
     struct XRegs {
-        double ma[4], fa[4], mb[4], fb[4];
+        f32x4 ma, fa, mb, fb;
     };
 
     __device__ __forceinline__ static void load_xregs(XRegs &x, const double *mean,
@@ -198,10 +200,10 @@ struct F32Tile {
         const int64_t ca = m0 + (tid % ALoader::CPR) * 4, cb = n0 + (tid % BLoader::CPR) * 4;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            x.ma[e] = ca + e < M ? mean[ca + e] : 0.0;
-            x.mb[e] = cb + e < N ? mean[cb + e] : 0.0;
-            x.fa[e] = XFORM == 2 && ca + e < M ? factor[ca + e] : 0.0;
-            x.fb[e] = XFORM == 2 && cb + e < N ? factor[cb + e] : 0.0;
+            x.ma[e] = ca + e < M ? (float)mean[ca + e] : 0.f;
+            x.mb[e] = cb + e < N ? (float)mean[cb + e] : 0.f;
+            x.fa[e] = XFORM == 2 && ca + e < M ? (float)factor[ca + e] : 0.f;
+            x.fb[e] = XFORM == 2 && cb + e < N ? (float)factor[cb + e] : 0.f;
         }
     }
 
@@ -235,22 +237,26 @@ struct F32Tile {
 
     __device__ __forceinline__ static void load_a(ALoader &la, const float *A, int64_t lda,
                                                   int64_t M, int64_t kend, int64_t m0, int64_t k0,
-                                                  int tid, bool v4)
+                                                  int tid, bool v4, const XRegs *xr)
     {
+        f32x4 fill = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (XFORM != 0) fill = xr->ma;
         if (A_KMAJOR)
-            la.load(A, lda, kend, M, k0, m0, tid, v4);
+            la.load(A, lda, kend, M, k0, m0, tid, v4, fill);
         else
-            la.load(A, lda, M, kend, m0, k0, tid, v4);
+            la.load(A, lda, M, kend, m0, k0, tid, v4, fill);
     }
 
     __device__ __forceinline__ static void load_b(BLoader &lb, const float *B, int64_t ldb,
                                                   int64_t N, int64_t kend, int64_t n0, int64_t k0,
-                                                  int tid, bool v4)
+                                                  int tid, bool v4, const XRegs *xr)
     {
+        f32x4 fill = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (XFORM != 0) fill = xr->mb;
         if (B_NMAJOR)
-            lb.load(B, ldb, N, kend, n0, k0, tid, v4);
+            lb.load(B, ldb, N, kend, n0, k0, tid, v4, fill);
         else
-            lb.load(B, ldb, kend, N, k0, n0, tid, v4);
+            lb.load(B, ldb, kend, N, k0, n0, tid, v4, fill);
     }
 
     // Four consecutive k values (kk + h4 .. + 3) of B column x from LDS.
@@ -372,16 +378,16 @@ struct F32Tile {
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
         ALoader la1;
         BLoader lb1;
-        load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4);
-        load_b(lb1, B, ldb, N, kend, n0, kbeg + BK, tid, v4);
+        load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4, xr);
+        load_b(lb1, B, ldb, N, kend, n0, kbeg + BK, tid, v4, xr);
         __syncthreads();
         Frag f;
         read_frag(As, Bs, 0, wm0, wn0, lane, f);
         int64_t kt = 0;
         for (; kt + 2 <= nk; kt += 2) {
             const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
-            load_a(la, A, lda, M, kend, m0, k2, tid, v4);
-            load_b(lb, B, ldb, N, kend, n0, k2, tid, v4);
+            load_a(la, A, lda, M, kend, m0, k2, tid, v4, xr);
+            load_b(lb, B, ldb, N, kend, n0, k2, tid, v4, xr);
             kloop(As, Bs, f, acc, wm0, wn0, lane);
             store_a(la1, As + A_STAGE, tid, xr);
             store_b(lb1, Bs + B_STAGE, tid, xr);
@@ -392,8 +398,8 @@ struct F32Tile {
                 mma(f, acc);
                 f = g;
             }
-            load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
-            load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4);
+            load_a(la1, A, lda, M, kend, m0, k3, tid, v4, xr);
+            load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4, xr);
             kloop(As + A_STAGE, Bs + B_STAGE, f, acc, wm0, wn0, lane);
             if (kt + 2 < nk) {
                 store_a(la, As, tid, xr);
@@ -634,8 +640,8 @@ struct F32Tile {
         }
         ALoader la;
         BLoader lb;
-        load_a(la, A, lda, M, kend, m0, kbeg, tid, v4);
-        load_b(lb, B, ldb, N, kend, n0, kbeg, tid, v4);
+        load_a(la, A, lda, M, kend, m0, kbeg, tid, v4, xr);
+        load_b(lb, B, ldb, N, kend, n0, kbeg, tid, v4, xr);
         store_a(la, As, tid, xr);
         store_b(lb, Bs, tid, xr);
         if (PF == 3) {
@@ -651,20 +657,20 @@ struct F32Tile {
             // compiler's wait counts stay exact).
             ALoader la1;
             BLoader lb1;
-            load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4);
-            load_b(lb1, B, ldb, N, kend, n0, kbeg + BK, tid, v4);
+            load_a(la1, A, lda, M, kend, m0, kbeg + BK, tid, v4, xr);
+            load_b(lb1, B, ldb, N, kend, n0, kbeg + BK, tid, v4, xr);
             __syncthreads();
             int64_t kt = 0;
             for (; kt + 2 <= nk; kt += 2) {
                 const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
-                load_a(la, A, lda, M, kend, m0, k2, tid, v4);
-                load_b(lb, B, ldb, N, kend, n0, k2, tid, v4);
+                load_a(la, A, lda, M, kend, m0, k2, tid, v4, xr);
+                load_b(lb, B, ldb, N, kend, n0, k2, tid, v4, xr);
                 compute(As, Bs, acc, wm0, wn0, lane);
                 store_a(la1, As + A_STAGE, tid, xr);
                 store_b(lb1, Bs + B_STAGE, tid, xr);
                 __syncthreads();
-                load_a(la1, A, lda, M, kend, m0, k3, tid, v4);
-                load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4);
+                load_a(la1, A, lda, M, kend, m0, k3, tid, v4, xr);
+                load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4, xr);
                 compute(As + A_STAGE, Bs + B_STAGE, acc, wm0, wn0, lane);
                 if (kt + 2 < nk) {
                     store_a(la, As, tid, xr);
@@ -684,8 +690,8 @@ struct F32Tile {
             const bool more = kt + 1 < nk;
             if (more) {
                 const int64_t k1 = kbeg + (kt + 1) * BK;
-                load_a(la, A, lda, M, kend, m0, k1, tid, v4);
-                load_b(lb, B, ldb, N, kend, n0, k1, tid, v4);
+                load_a(la, A, lda, M, kend, m0, k1, tid, v4, xr);
+                load_b(lb, B, ldb, N, kend, n0, k1, tid, v4, xr);
             }
             compute(As + cur * A_STAGE, Bs + cur * B_STAGE, acc, wm0, wn0, lane);
             if (more) {
@@ -791,11 +797,15 @@ struct F32Tile {
     // mode 0: value * scale; mode 1: value, diagonal forced to 1.0;
     // mode 2: S = scale * value + beta * S at both positions (the symmetric
     // rank updates; S is then symmetric only if it was before).
+    // vtid: the thread of the tile whose accumulators acc holds (default:
+    // this thread).
     __device__ __forceinline__ static void epilogue_syrk(const f32x16 (&acc)[TM][TN], float *S,
                                                          int64_t M, int64_t m0, int64_t n0,
-                                                         int mode, float scale, float beta = 0.f)
+                                                         int mode, float scale, float beta = 0.f,
+                                                         int vtid = -1)
     {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int tid = vtid >= 0 ? vtid : (int)threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
         const bool diag_tile = m0 == n0;
 #pragma unroll

@@ -224,22 +224,32 @@ __global__ __launch_bounds__(kMvThreads) void mv_kernel(MvArgs a)
     }
 }
 
-// out[j] (=, +=) sum over row groups of part[g][j], in group order taken
-// four interleaved running sums at a time (fixed order: deterministic).
-__global__ __launch_bounds__(256) void mv_finish_cols(const float *__restrict__ part, int groups,
-                                                      int64_t N, int add, float *__restrict__ out)
+// out[j] (=, +=) sum over row groups of part[g][j].  A work-group of 8
+// waves takes 64 columns; wave w adds the w-th eighth of the groups in group
+// order, then the eight sums are added in wave order through LDS (a fixed
+// order: deterministic).
+constexpr int kFinWaves = 8;
+
+__global__ __launch_bounds__(64 * kFinWaves) void mv_finish_cols(const float *__restrict__ part,
+                                                                 int groups, int64_t N, int add,
+                                                                 float *__restrict__ out)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= N) return;
-    float s[4] = {0.f, 0.f, 0.f, 0.f};
-    int g = 0;
-    for (; g + 4 <= groups; g += 4) {
+    __shared__ float sums[kFinWaves][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int per = (groups + kFinWaves - 1) / kFinWaves;
+    const int g0 = wave * per, g1 = g0 + per < groups ? g0 + per : groups;
+    float s = 0.f;
+    if (j < N)
+        for (int g = g0; g < g1; ++g) s += part[(int64_t)g * N + j];
+    sums[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && j < N) {
+        float t = sums[0][lane];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[q] += part[(int64_t)(g + q) * N + j];
+        for (int w = 1; w < kFinWaves; ++w) t += sums[w][lane];
+        out[j] = add ? out[j] + t : t;
     }
-    for (; g < groups; ++g) s[g & 3] += part[(int64_t)g * N + j];
-    const float t = (s[0] + s[1]) + (s[2] + s[3]);
-    out[j] = add ? out[j] + t : t;
 }
 
 // Row products from slab partials, slab order, then the row epilogue.
@@ -270,12 +280,13 @@ MvPlan mv_plan(int64_t M, int64_t N, int max_nch, bool two_matrices)
     const int64_t w = (int64_t)1024 * p.nch;
     p.slabs = (int)((N + w - 1) / w);
     if (p.slabs < 1) p.slabs = 1;
-    // rows per step: about 32 registers of row data per thread (64 for
-    // the widest fused slab, which holds one row)
-    p.rb = p.nch >= 8 ? 1 : 8 / p.nch;
+    // rows per step: 64 KiB of a matrix in flight per work-group and step
+    // (64 registers of row data per thread)
+    p.rb = p.nch >= 16 ? 1 : 16 / p.nch;
     if (two_matrices && p.rb > 1) p.rb /= 2;
-    int64_t groups = (M + 31) / 32;
-    const int64_t cap = 1024 / p.slabs > 1 ? 1024 / p.slabs : 1;
+    // row groups of at least 16 rows, about 512 work-groups in all
+    int64_t groups = (M + 15) / 16;
+    const int64_t cap = 512 / p.slabs > 1 ? 512 / p.slabs : 1;
     if (groups > cap) groups = cap;
     if (groups < 1) groups = 1;
     p.rows_per = (M + groups - 1) / groups;
@@ -303,10 +314,10 @@ int launch_pass(const MvPlan &p, MvArgs a, hipStream_t s)
         return (int)hipGetLastError();                                                          \
     }
     if constexpr ((OPS & kDotB) == 0) {
-        LI_MV(1, 8) LI_MV(2, 4) LI_MV(4, 2) LI_MV(8, 1)
+        LI_MV(1, 16) LI_MV(2, 8) LI_MV(4, 4) LI_MV(8, 2)
         if constexpr ((OPS & kColFromDot) != 0) { LI_MV(16, 1) }
     } else {
-        LI_MV(1, 4) LI_MV(2, 2) LI_MV(4, 1) LI_MV(8, 1)
+        LI_MV(1, 8) LI_MV(2, 4) LI_MV(4, 2) LI_MV(8, 1)
     }
 #undef LI_MV
     return (int)hipErrorInvalidValue;
@@ -314,9 +325,9 @@ int launch_pass(const MvPlan &p, MvArgs a, hipStream_t s)
 
 int finish_cols(const MvPlan &p, const MvArgs &a, int add, float *out, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((a.N + 255) / 256);
-    hipLaunchKernelGGL(mv_finish_cols, dim3(blocks), dim3(256), 0, s, (const float *)a.col_part,
-                       p.groups, a.N, add, out);
+    const unsigned blocks = (unsigned)((a.N + 63) / 64);
+    hipLaunchKernelGGL(mv_finish_cols, dim3(blocks), dim3(64 * kFinWaves), 0, s,
+                       (const float *)a.col_part, p.groups, a.N, add, out);
     return (int)hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "f32_tile.h"
+#include "li_internal.h"
 
 namespace li {
 
@@ -52,6 +53,39 @@ __device__ __forceinline__ void sym_reduce(float *lds, const SymArgs &a, int64_t
     T::mainloop(lds, a.X, a.ld, FORM == kSymRows2 ? a.Z : a.X, a.ld, a.n, a.n, kbeg, kend, m0, n0,
                 acc);
     if (FORM == kSymRows2) T::mainloop(lds, a.Z, a.ld, a.X, a.ld, a.n, a.n, kbeg, kend, m0, n0, acc);
+}
+
+// Raw accumulators of one tile as a partial result: BM * BN floats, laid out
+// chunk-major ([chunk][thread] float4s, chunk = 4 consecutive registers), so
+// one store or load instruction of a wave touches 1 KiB contiguously.
+template <class T>
+__device__ __forceinline__ void store_partial(const f32x16 (&acc)[T::TM][T::TN], float *dst, int tid)
+{
+    f32x4 *d = reinterpret_cast<f32x4 *>(dst);
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                d[((i * T::TN + j) * 4 + q) * T::NT + tid] =
+                    f32x4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+}
+
+template <class T>
+__device__ __forceinline__ void add_partial(f32x16 (&acc)[T::TM][T::TN], const float *src, int tid)
+{
+    const f32x4 *p = reinterpret_cast<const f32x4 *>(src);
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 x = p[((i * T::TN + j) * 4 + q) * T::NT + tid];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] += x[e];
+            }
 }
 
 template <class T, int FORM>
@@ -92,62 +126,148 @@ __global__ __launch_bounds__(T::NT) void sym_split_kernel(SymArgs a, float *__re
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
     sym_reduce<T, FORM>(lds, a, kbeg, kend, m0, n0, acc);
-    constexpr int R = 16 * T::TM * T::TN;
-    f32x4 *dst = reinterpret_cast<f32x4 *>(part + ((int64_t)(sidx * nb + t) * T::NT + threadIdx.x) * R);
-#pragma unroll
-    for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-        for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                dst[(i * T::TN + j) * 4 + q] =
-                    f32x4{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+    store_partial<T>(acc, part + (int64_t)(sidx * nb + t) * T::BM * T::BN, threadIdx.x);
+}
+
+// Reduce kernel: 256-thread work-groups, T::NT / 256 per tile, each taking
+// the partials of one slice of the tile's threads (so a 16-wave tile is
+// reduced by four work-groups).
+constexpr int kReduceThreads = 256;
+
+template <class T>
+__global__ __launch_bounds__(kReduceThreads) void sym_split_reduce_kernel(SymArgs a,
+                                                                          const float *__restrict__ part,
+                                                                          int tiles, int splits)
+{
+    static_assert(T::NT % kReduceThreads == 0, "tile threads must split into reduce slices");
+    constexpr int SLICES = T::NT / kReduceThreads;
+    const int nb = tiles * (tiles + 1) / 2;
+    const int t = blockIdx.x / SLICES;
+    const int vtid = (blockIdx.x % SLICES) * kReduceThreads + threadIdx.x;
+    int tm, tn;
+    upper_tile(t, tiles, tm, tn);
+    f32x16 acc[T::TM][T::TN];
+    T::zero(acc);
+    for (int s = 0; s < splits; ++s) add_partial<T>(acc, part + (int64_t)(s * nb + t) * T::BM * T::BN, vtid);
+    T::epilogue_syrk(acc, a.S, a.n, (int64_t)tm * T::BM, (int64_t)tn * T::BN, a.mode, a.scale, a.beta,
+                     vtid);
+}
+
+// ------------------------------------------------------------ stream-K
+// The nb upper tiles times kt K-tiles form one iteration space; work-group
+// g of G takes iterations [g total / G, (g + 1) total / G), so every
+// work-group does the same amount of reduction whatever nb is (the split
+// above quantises nb * splits work-groups onto the compute units).  A range
+// covers whole tiles (written directly) and at most two tile pieces: its
+// first segment (partial slot 0) and its last (slot 1).  The fixup kernel
+// adds the pieces of every shared tile in work-group order (deterministic)
+// and runs the epilogue.
+constexpr int kStreamMaxGroups = 512;
+
+__host__ __device__ __forceinline__ int64_t sk_begin(int64_t g, int64_t total, int G)
+{
+    return g * total / G;
+}
+
+// the work-group whose range contains iteration i
+__device__ __forceinline__ int sk_owner(int64_t i, int64_t total, int G)
+{
+    return (int)(((i + 1) * G + total - 1) / total - 1);
+}
+
+template <class T, int FORM>
+__global__ __launch_bounds__(T::NT) void sym_streamk_kernel(SymArgs a, float *__restrict__ part,
+                                                            int tiles, int kt)
+{
+    __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    const int nb = tiles * (tiles + 1) / 2;
+    const int G = gridDim.x;
+    const int g = blockIdx.x;
+    const int64_t total = (int64_t)nb * kt;
+    const int64_t beg = sk_begin(g, total, G), end = sk_begin(g + 1, total, G);
+    for (int64_t it = beg; it < end;) {
+        const int t = (int)(it / kt);
+        const int64_t tile_end = (int64_t)(t + 1) * kt;
+        const int64_t stop = end < tile_end ? end : tile_end;
+        const int64_t k0 = it - (int64_t)t * kt, k1 = stop - (int64_t)t * kt;
+        int tm, tn;
+        upper_tile(t, tiles, tm, tn);
+        const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
+        const int64_t kend = k1 * T::BK < a.kdim ? k1 * T::BK : a.kdim;
+        f32x16 acc[T::TM][T::TN];
+        T::zero(acc);
+        sym_reduce<T, FORM>(lds, a, k0 * T::BK, kend, m0, n0, acc);
+        if (k0 == 0 && k1 == kt)
+            T::epilogue_syrk(acc, a.S, a.n, m0, n0, a.mode, a.scale, a.beta);
+        else
+            store_partial<T>(acc, part + ((int64_t)g * 2 + (it == beg ? 0 : 1)) * T::BM * T::BN,
+                             threadIdx.x);
+        it = stop;
+    }
 }
 
 template <class T>
-__global__ __launch_bounds__(T::NT) void sym_split_reduce_kernel(SymArgs a,
-                                                                 const float *__restrict__ part,
-                                                                 int tiles, int splits)
+__global__ __launch_bounds__(kReduceThreads) void sym_streamk_fixup_kernel(SymArgs a,
+                                                                           const float *__restrict__ part,
+                                                                           int tiles, int kt, int G)
 {
+    constexpr int SLICES = T::NT / kReduceThreads;
     const int nb = tiles * (tiles + 1) / 2;
-    const int t = blockIdx.x;
+    const int t = blockIdx.x / SLICES;
+    const int vtid = (blockIdx.x % SLICES) * kReduceThreads + threadIdx.x;
+    const int64_t total = (int64_t)nb * kt;
+    const int g0 = sk_owner((int64_t)t * kt, total, G), g1 = sk_owner((int64_t)(t + 1) * kt - 1, total, G);
+    if (g0 == g1) return;  // one work-group reduced the whole tile
     int tm, tn;
     upper_tile(t, tiles, tm, tn);
-    constexpr int R = 16 * T::TM * T::TN;
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
-    for (int s = 0; s < splits; ++s) {
-        const f32x4 *src =
-            reinterpret_cast<const f32x4 *>(part + ((int64_t)(s * nb + t) * T::NT + threadIdx.x) * R);
-#pragma unroll
-        for (int i = 0; i < T::TM; ++i)
-#pragma unroll
-            for (int j = 0; j < T::TN; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const f32x4 x = src[(i * T::TN + j) * 4 + q];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] += x[e];
-                }
+    for (int g = g0; g <= g1; ++g) {
+        // the tile is g's first segment unless g started in an earlier tile
+        const int slot = sk_begin(g, total, G) / kt == t ? 0 : 1;
+        add_partial<T>(acc, part + ((int64_t)g * 2 + slot) * T::BM * T::BN, vtid);
     }
-    T::epilogue_syrk(acc, a.S, a.n, (int64_t)tm * T::BM, (int64_t)tn * T::BN, a.mode, a.scale, a.beta);
+    T::epilogue_syrk(acc, a.S, a.n, (int64_t)tm * T::BM, (int64_t)tn * T::BN, a.mode, a.scale, a.beta,
+                     vtid);
 }
 
 // Bytes of split-K partials a candidate list may need for order n.
+// (split_k == 0 marks the stream-K schedule: two pieces per work-group)
 #define LI_SYM_SPLIT_BYTES(IDX, BM, BN, BK, WM, WN, SK, PF)                                        \
     if (SK > 1) {                                                                                \
         const int64_t t = (n + BM - 1) / BM;                                                     \
         const size_t b = (size_t)SK * (size_t)(t * (t + 1) / 2) * BM * BN * sizeof(float);       \
         if (b > best) best = b;                                                                  \
+    } else if (SK == 0) {                                                                        \
+        const size_t b = (size_t)2 * kStreamMaxGroups * BM * BN * sizeof(float);                 \
+        if (b > best) best = b;                                                                  \
     }
 
-// Enqueue one symmetric contraction with tile type T.  splits > 1 needs the
+// Enqueue one symmetric contraction with tile type T.  splits > 1 (split
+// reduction) and splits == 0 (stream-K over `groups` work-groups) need the
 // partial workspace `ws`.
 template <class T, int FORM>
 int run_sym(const SymArgs &a, int splits, float *ws, hipStream_t s)
 {
+    // stream-K work-groups: as many as are resident at once (one 16-wave
+    // work-group per compute unit, two of the smaller ones)
+    const int groups = device_cu_count() * (T::NT >= 1024 ? 1 : 2);
     const int tiles = (int)((a.n + T::BM - 1) / T::BM);
     const int nb = tiles * (tiles + 1) / 2;
+    if (splits == 0 && a.reads && a.kdim > 0) {
+        if (!ws) return (int)hipErrorInvalidValue;
+        const int kt = (int)((a.kdim + T::BK - 1) / T::BK);
+        const int64_t total = (int64_t)nb * kt;
+        int G = groups < kStreamMaxGroups ? groups : kStreamMaxGroups;
+        if (G > total) G = (int)total;
+        if (G < 1) G = 1;
+        hipLaunchKernelGGL((sym_streamk_kernel<T, FORM>), dim3(G), dim3(T::NT), 0, s, a, ws, tiles, kt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (int)e;
+        hipLaunchKernelGGL(sym_streamk_fixup_kernel<T>, dim3(nb * (T::NT / kReduceThreads)),
+                           dim3(kReduceThreads), 0, s, a, (const float *)ws, tiles, kt, G);
+        return (int)hipGetLastError();
+    }
     if (splits <= 1 || !a.reads || a.kdim == 0) {
         hipLaunchKernelGGL((sym_kernel<T, FORM>), dim3(nb), dim3(T::NT), 0, s, a, tiles);
         return (int)hipGetLastError();
@@ -159,8 +279,8 @@ int run_sym(const SymArgs &a, int splits, float *ws, hipStream_t s)
                        tiles, splits, kchunk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(sym_split_reduce_kernel<T>, dim3(nb), dim3(T::NT), 0, s, a, (const float *)ws,
-                       tiles, splits);
+    hipLaunchKernelGGL(sym_split_reduce_kernel<T>, dim3(nb * (T::NT / kReduceThreads)),
+                       dim3(kReduceThreads), 0, s, a, (const float *)ws, tiles, splits);
     return (int)hipGetLastError();
 }
 

@@ -153,23 +153,30 @@ def run_fused(li, X, corr, eps=0.1):
     return host(mean), (host(std) if corr else None), host(out)
 
 
+# the fused loads centre in FP32 with the mean split into two floats: each
+# centred value is within about one rounding of the FP64 centring, so the
+# contraction agrees with the two-kernel path to a few ulp
+FUSED_VS_UNFUSED = 2e-6
+
+
 @pytest.mark.parametrize("N,M", [(2, 1), (37, 5), (300, 129), (513, 600), (1000, 250)])
-def test_fused_equals_unfused_bitwise(li, orc, N, M):
-    # the fused loads apply the centring kernel's arithmetic element by
-    # element, so every result is bitwise that of the two-kernel path
+def test_fused_against_oracle_and_unfused(li, orc, N, M):
     say("fused stats", N, M)
     X = synth.stats_inputs(N, M, seed=45)["data"]
     if M > 3:
         X[:, 3] = 0.05 * X[:, 3]
+    _, _, rcov = orc.covariance(X, want_y=False)
+    _, _, _, rcorr = orc.correlation(X, want_y=False)
     for corr in (False, True):
         _, mean, std, out = run_stats(li, X, corr=corr)
         fmean, fstd, fout = run_fused(li, X, corr=corr)
         assert np.array_equal(mean, fmean)
-        assert np.array_equal(out, fout), corr
         if corr:
             assert np.array_equal(std, fstd)
-    _, _, rcov = orc.covariance(X, want_y=False)
-    assert normwise(run_fused(li, X, False)[2], rcov) < TOL_FP32
+            assert np.all(np.diag(fout) == 1.0)
+        assert np.array_equal(fout, fout.T)
+        assert normwise(fout, out) < FUSED_VS_UNFUSED, corr
+        assert normwise(fout, rcorr if corr else rcov) < TOL_FP32, corr
 
 
 def test_fused_every_tile_shape(li, orc):
@@ -182,7 +189,7 @@ def test_fused_every_tile_shape(li, orc):
             li.li_tune_force(li.LI_KERNEL_SYRK_F32, cfg)
             _, _, _, corr = run_stats(li, X, corr=True)
             _, _, fcorr = run_fused(li, X, corr=True)
-            assert np.array_equal(corr, fcorr), cfg
+            assert normwise(fcorr, corr) < FUSED_VS_UNFUSED, cfg
             assert normwise(fcorr, rcorr) < TOL_FP32, cfg
     finally:
         li.li_tune_force(li.LI_KERNEL_SYRK_F32, -1)
@@ -203,10 +210,17 @@ def test_fused_constant_columns(li):
         assert np.all(np.delete(corr[j, :], j) == 0.0)
 
 
-def test_fused_config2_bitwise(li):
+def test_fused_config2(li, orc):
     say("fused stats 4096 x 2048")
     X = synth.config(2)["data"]
+    N, M = X.shape
+    pa = synth.integer_matrix(48, "pa", (100,), 0, M - 1).astype(np.int64)
+    pb = synth.integer_matrix(48, "pb", (100,), 0, M - 1).astype(np.int64)
     for corr in (False, True):
         _, mean, std, out = run_stats(li, X, corr=corr)
         fmean, fstd, fout = run_fused(li, X, corr=corr)
-        assert np.array_equal(out, fout) and np.array_equal(mean, fmean)
+        assert np.array_equal(mean, fmean)
+        assert normwise(fout, out) < FUSED_VS_UNFUSED
+        ref = orc.correlation_entries(X, pa, pb) if corr else orc.covariance_entries(X, pa, pb)
+        scale = 1.0 if corr else np.max(np.abs(np.diag(fout)))
+        assert np.max(np.abs(fout[pa, pb] - ref)) / scale < TOL_FP32
