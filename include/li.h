@@ -281,7 +281,9 @@ typedef struct li_tile_config {
     int32_t prefetch;       /* main-loop mode 1-4 (1, 2: K-tiles in flight
                                from HBM; 3: 2 plus operand reads pipelined
                                across the barrier; 4: direct HBM-to-LDS
-                               loads into a three-stage ring)           */
+                               loads into a three-stage ring); FP32 GEMM
+                               5-7: modes 1-3 with B transposed into LDS
+                               so both operands take 16-byte LDS reads */
 } li_tile_config;
 
 int32_t li_tune_num_candidates(int32_t kernel);

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace li {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -52,6 +54,15 @@ __device__ __forceinline__ void grouped_tile(int t, int tiles_m, int tiles_n, in
     tn = in / gm;
 }
 
+// 16 zero bytes in device memory: loads of elements outside a matrix read
+// them instead of selecting zeros after the load, so no instruction waits
+// on a load before its data is needed.
+__device__ __forceinline__ const float *zero_src()
+{
+    static __device__ const float z[4] __attribute__((aligned(16))) = {0.f, 0.f, 0.f, 0.f};
+    return z;
+}
+
 // Global-load modes: scalar loads, 16-byte vector loads, or either chosen at
 // run time by a flag (one code path for problems of both kinds).
 enum { kLoadScalar = 0, kLoadVec4 = 1, kLoadDynamic = 2 };
@@ -61,10 +72,8 @@ enum { kLoadScalar = 0, kLoadVec4 = 1, kLoadDynamic = 2 };
 // consecutive columns per chunk, zero-filling everything outside the matrix.
 // Vector loads require cols % 4 == 0, ld % 4 == 0 and a 16-byte aligned base.
 // The loads are unconditional: a lane whose chunk lies outside the matrix
-// reads the matrix's first element(s) instead (always valid: a load happens
-// only when rows, cols >= 1, and cols >= 4 with vector loads) and keeps
-// zeros.  Without branches around loads the compiler can issue them all at
-// once and count them exactly in its waits.
+// reads zero_src() instead.  Without branches around loads the compiler can
+// issue them all at once and count them exactly in its waits.
 template <int TR, int TC, int NT, int MODE>
 struct TileLoader {
     static constexpr int CPR = TC / 4;
@@ -74,8 +83,10 @@ struct TileLoader {
     static constexpr int PER = NCH / NT;
     f32x4 v[PER];
 
-    // Elements outside the matrix take the value `fill` (per column of the
-    // chunk; zeros unless a transform at the store maps fill to zero).
+    // Elements outside the matrix are zero, or with FILLED take the value
+    // `fill` (per column of the chunk; a transform at the store maps it to
+    // zero) selected after the load.
+    template <bool FILLED = false>
     __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
                                          int64_t cols, int64_t r0, int64_t c0, int tid,
                                          bool dyn_vec4, f32x4 fill = f32x4{0.f, 0.f, 0.f, 0.f})
@@ -89,15 +100,23 @@ struct TileLoader {
             const bool rok = gr < rows;
             if (vec4) {
                 const bool ok = rok && gc < cols;
-                const f32x4 x = *reinterpret_cast<const f32x4 *>(p + (ok ? gr * ld + gc : 0));
-                v[i] = ok ? x : fill;
+                if (FILLED) {
+                    const f32x4 x = *reinterpret_cast<const f32x4 *>(p + (ok ? gr * ld + gc : 0));
+                    v[i] = ok ? x : fill;
+                } else {
+                    v[i] = *reinterpret_cast<const f32x4 *>(ok ? p + gr * ld + gc : zero_src());
+                }
             } else {
                 const int64_t base = gr * ld + gc;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const bool ok = rok && gc + e < cols;
-                    const float x = p[ok ? base + e : 0];
-                    v[i][e] = ok ? x : fill[e];
+                    if (FILLED) {
+                        const float x = p[ok ? base + e : 0];
+                        v[i][e] = ok ? x : fill[e];
+                    } else {
+                        v[i][e] = *(ok ? p + base + e : zero_src());
+                    }
                 }
             }
         }
@@ -138,19 +157,68 @@ struct TileLoader {
     }
 };
 
+// Copies a TK x TC tile of a row-major matrix (rows = k) into LDS
+// transposed, [TC][LDL] with k contiguous, so matrix-core operands can be
+// read four k at a time with one 16-byte LDS read.  Each piece is 4
+// consecutive k of one column: four scalar loads (consecutive lanes take
+// consecutive columns, so every load instruction is coalesced) and one
+// 16-byte LDS store.  Elements outside the matrix read zero_src(); loads
+// are unconditional, as in TileLoader.
+template <int TK, int TC, int NT>
+struct TileLoaderKT {
+    static constexpr int NPC = (TK / 4) * TC;
+    static_assert(TK % 4 == 0 && NPC % NT == 0, "pieces must divide evenly among threads");
+    static constexpr int PER = NPC / NT;
+    f32x4 v[PER];
+
+    __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
+                                         int64_t cols, int64_t r0, int64_t c0, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int pc = tid + i * NT;
+            const int c = pc % TC, kq = pc / TC;
+            const int64_t gc = c0 + c;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gr = r0 + 4 * kq + e;
+                const bool ok = gr < rows && gc < cols;
+                v[i][e] = *(ok ? p + gr * ld + gc : zero_src());
+            }
+        }
+    }
+
+    template <int LDL>
+    __device__ __forceinline__ void store(float *lds, int tid) const
+    {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int pc = tid + i * NT;
+            const int c = pc % TC, kq = pc / TC;
+            *reinterpret_cast<f32x4 *>(lds + c * LDL + 4 * kq) = v[i];
+        }
+    }
+};
+
 // One work-group computes a BM x BN block tile with WM x WN waves; each wave
 // owns a (BM/WM) x (BN/WN) sub-tile made of TM x TN 32x32 accumulator blocks.
 // A_KMAJOR: A element (m, k) is at A[k*lda + m] (the transposed operand of
 // the column-form symmetric contraction); otherwise at A[m*lda + k].
 // B_NMAJOR: B element (k, n) is at B[n*ldb + k] (the transposed operand of
 // the row-form symmetric updates A A^T); otherwise at B[k*ldb + n].
+// B_LDST: a row-major B is transposed on its way into LDS (TileLoaderKT),
+// so both operands are read with 16-byte LDS reads.
 // LOAD: kLoadScalar, kLoadVec4 or kLoadDynamic (flag passed to mainloop).
 // PF: K-tiles in flight from HBM (1: the next tile; 2: the next two; 3: the
 // next two, with LDS operand reads pipelined across the barrier; 4: direct
 // HBM-to-LDS loads into a three-stage ring, vector loads only).
 template <int BM_, int BN_, int BK_, int WM_, int WN_, bool A_KMAJOR, int LOAD, int PF = 1,
-          bool B_NMAJOR = false, int XFORM_ = 0>
+          bool B_NMAJOR = false, int XFORM_ = 0, bool B_LDST = false>
 struct F32Tile {
+    static_assert(!(B_LDST && (B_NMAJOR || PF == 4)),
+                  "the transposing B loader is for row-major B through registers");
+    // B is k-contiguous in LDS
+    static constexpr bool BT = B_NMAJOR || B_LDST;
     static_assert(PF >= 1 && PF <= 4, "prefetch mode is 1 to 4");
     // XFORM: 0 operands used as loaded; 1 / 2: both k-major operands are
     // raw data, centred (1) or normalised (2) column by column on their way
@@ -169,15 +237,17 @@ struct F32Tile {
     // [BK][width+8] (lanes read consecutive m / n of one k row).
     static constexpr int A_LD = A_KMAJOR ? BM + 8 : BK + 4;
     static constexpr int A_STAGE = (A_KMAJOR ? BK : BM) * A_LD;
-    static constexpr int B_LD = B_NMAJOR ? BK + 4 : BN + 8;
-    static constexpr int B_STAGE = (B_NMAJOR ? BN : BK) * B_LD;
+    static constexpr int B_LD = BT ? BK + 4 : BN + 8;
+    static constexpr int B_STAGE = (BT ? BN : BK) * B_LD;
     // PF == 4 keeps three unpadded, XOR-swizzled stages filled by direct
     // HBM-to-LDS loads (see mainloop_dma).
     static constexpr int DMA_A = BM * BK, DMA_B = BK * BN;
     static constexpr int LDS_FLOATS = PF == 4 ? 3 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
-    using BLoader = TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>;
+    using BLoader =
+        typename std::conditional<B_LDST, TileLoaderKT<BK, BN, NT>,
+                                  TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>>::type;
 
     // Per-thread column statistics for XFORM: the four columns of A (m) and
     // of B (n) that this thread's chunks cover, mean rounded to FP32 and
@@ -242,9 +312,9 @@ struct F32Tile {
         f32x4 fill = f32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (XFORM != 0) fill = xr->ma;
         if (A_KMAJOR)
-            la.load(A, lda, kend, M, k0, m0, tid, v4, fill);
+            la.template load<XFORM != 0>(A, lda, kend, M, k0, m0, tid, v4, fill);
         else
-            la.load(A, lda, M, kend, m0, k0, tid, v4, fill);
+            la.template load<XFORM != 0>(A, lda, M, kend, m0, k0, tid, v4, fill);
     }
 
     __device__ __forceinline__ static void load_b(BLoader &lb, const float *B, int64_t ldb,
@@ -253,17 +323,19 @@ struct F32Tile {
     {
         f32x4 fill = f32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (XFORM != 0) fill = xr->mb;
-        if (B_NMAJOR)
-            lb.load(B, ldb, N, kend, n0, k0, tid, v4, fill);
+        if constexpr (B_LDST)
+            lb.load(B, ldb, kend, N, k0, n0, tid);
+        else if constexpr (B_NMAJOR)
+            lb.template load<XFORM != 0>(B, ldb, N, kend, n0, k0, tid, v4, fill);
         else
-            lb.load(B, ldb, kend, N, k0, n0, tid, v4, fill);
+            lb.template load<XFORM != 0>(B, ldb, kend, N, k0, n0, tid, v4, fill);
     }
 
     // Four consecutive k values (kk + h4 .. + 3) of B column x from LDS.
     __device__ __forceinline__ static void read_b4(const float *Bs, int kk, int h4, int x,
                                                    float (&b)[4])
     {
-        if (B_NMAJOR) {
+        if (BT) {
             const f32x4 t = *reinterpret_cast<const f32x4 *>(Bs + x * B_LD + kk + h4);
             b[0] = t[0];
             b[1] = t[1];
@@ -443,11 +515,7 @@ struct F32Tile {
     }
     __device__ __forceinline__ static int swz_k(int k) { return ((k >> 2) & 1) << 3; }
 
-    __device__ __forceinline__ static const float *zero16()
-    {
-        static __device__ const float z[4] __attribute__((aligned(16))) = {0.f, 0.f, 0.f, 0.f};
-        return z;
-    }
+    __device__ __forceinline__ static const float *zero16() { return zero_src(); }
     static_assert(PF != 4 || BK == 32 || BK == 64, "direct LDS loads use K-tiles of 32 or 64");
 
     __device__ __forceinline__ static void lds_dma(const float *src, float *dst)
