@@ -200,6 +200,59 @@ struct TileLoaderKT {
     }
 };
 
+// The same transposing copy in 4 x 4 blocks: four 16-byte loads (four k
+// rows of four consecutive columns; consecutive lanes take consecutive
+// column quads, so each load instruction is coalesced), transposed in
+// registers into four 16-byte LDS stores.  Vector loads need cols % 4 == 0,
+// ld % 4 == 0 and an aligned base (MODE kLoadVec4); otherwise scalar loads.
+template <int TK, int TC, int NT, int MODE>
+struct TileLoaderKT4 {
+    static constexpr int QC = TC / 4;
+    static constexpr int NBLK = (TK / 4) * QC;
+    static_assert(TK % 4 == 0 && TC % 4 == 0 && NBLK % NT == 0, "blocks must divide among threads");
+    static constexpr int PER = NBLK / NT;
+    f32x4 v[PER][4];
+
+    __device__ __forceinline__ void load(const float *__restrict__ p, int64_t ld, int64_t rows,
+                                         int64_t cols, int64_t r0, int64_t c0, int tid)
+    {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int blk = tid + i * NT;
+            const int cq = blk % QC, kq = blk / QC;
+            const int64_t gc = c0 + 4 * cq;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gr = r0 + 4 * kq + j;
+                if (MODE == kLoadVec4) {
+                    const bool ok = gr < rows && gc < cols;
+                    v[i][j] = *reinterpret_cast<const f32x4 *>(ok ? p + gr * ld + gc : zero_src());
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool ok = gr < rows && gc + e < cols;
+                        v[i][j][e] = *(ok ? p + gr * ld + gc + e : zero_src());
+                    }
+                }
+            }
+        }
+    }
+
+    template <int LDL>
+    __device__ __forceinline__ void store(float *lds, int tid) const
+    {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int blk = tid + i * NT;
+            const int cq = blk % QC, kq = blk / QC;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                *reinterpret_cast<f32x4 *>(lds + (4 * cq + e) * LDL + 4 * kq) =
+                    f32x4{v[i][0][e], v[i][1][e], v[i][2][e], v[i][3][e]};
+        }
+    }
+};
+
 // One work-group computes a BM x BN block tile with WM x WN waves; each wave
 // owns a (BM/WM) x (BN/WN) sub-tile made of TM x TN 32x32 accumulator blocks.
 // A_KMAJOR: A element (m, k) is at A[k*lda + m] (the transposed operand of
@@ -245,9 +298,13 @@ struct F32Tile {
     static constexpr int LDS_FLOATS = PF == 4 ? 3 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
-    using BLoader =
-        typename std::conditional<B_LDST, TileLoaderKT<BK, BN, NT>,
-                                  TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>>::type;
+    // transposing loads in 4 x 4 blocks when there are enough blocks for
+    // every thread, else in 4 x 1 pieces
+    static constexpr bool KT4 = ((BK / 4) * (BN / 4)) % NT == 0 && LOAD != kLoadDynamic;
+    using BLoader = typename std::conditional<
+        B_LDST,
+        typename std::conditional<KT4, TileLoaderKT4<BK, BN, NT, LOAD>, TileLoaderKT<BK, BN, NT>>::type,
+        TileLoader<(B_NMAJOR ? BN : BK), (B_NMAJOR ? BK : BN), NT, LOAD>>::type;
 
     // Per-thread column statistics for XFORM: the four columns of A (m) and
     // of B (n) that this thread's chunks cover, mean rounded to FP32 and
