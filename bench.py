@@ -76,6 +76,30 @@ class Timer:
         torch.cuda.synchronize()
         return s.elapsed_time(e) / reps  # ms per call
 
+    def stats(self, fn, reps, warmup):
+        """mean, median and min of per-call times (ms)."""
+        t = sorted(self.time_each(fn, reps, warmup))
+        return {"ms": round(sum(t) / len(t), 4), "ms_median": round(t[len(t) // 2], 4),
+                "ms_min": round(t[0], 4)}
+
+    def time_cold(self, fn, reps, flush):
+        """mean ms per call with the 256 MB MALL and the L2s flushed before
+        every call (a 512 MiB buffer is written first, outside the timed
+        events)."""
+        torch = self.torch
+        fn()
+        total = 0.0
+        for _ in range(reps):
+            flush.fill_(1.0)
+            s = torch.cuda.Event(enable_timing=True)
+            e = torch.cuda.Event(enable_timing=True)
+            s.record()
+            fn()
+            e.record()
+            torch.cuda.synchronize()
+            total += s.elapsed_time(e)
+        return total / reps
+
     def time_each(self, fn, reps, warmup):
         """per-call times (ms) for mean / median / min."""
         torch = self.torch
@@ -146,6 +170,10 @@ def main():
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
+    per_step = sorted(timer.time_each(step, args.steps, 0))
+    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    ms_cold = timer.time_cold(step, 10, flush)
+    del flush
     f1 = gemm_flops(NI, NJ, NK)
     f2 = gemm_flops(NI, NL, NJ)
     flops_step = f1 + f2
@@ -180,6 +208,9 @@ def main():
                      "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": committed_traffic()},
     }
 
+    out["step_ms_stats"] = {"median": round(per_step[len(per_step) // 2], 4),
+                            "min": round(per_step[0], 4),
+                            "cold_cache_mean": round(ms_cold, 4)}
     if not args.main_only:
         out["rows"] = measure_rows(args, torch, li, synth, timer)
 
@@ -226,6 +257,18 @@ def cpu_baseline(c, D_gpu, flops_step, min_seconds=8.0):
     base = {"value": round(runs * flops_step / dt / 1e9, 2), "unit": "GFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "the full 2mm 2048^4 workload (34.4 GFLOP) run %d times, %.1f s" % (runs, dt)}
+    # the plain method on one core: 256 sampled rows of the same workload
+    # (the oracle computes rows independently), scaled to the whole step
+    rows = np.arange(0, c["NI"], c["NI"] // 256)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.mm2(c["A"], c["B"], c["C"], c["D"], alpha=c["alpha"], beta=c["beta"], rows=rows)
+    dt1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
+    base["single_thread"] = {"value": round(flops_step * len(rows) / c["NI"] / dt1 / 1e9, 2),
+                             "unit": "GFLOP/s", "cores": 1,
+                             "sample": "%d of %d rows of the 2mm workload, %.1f s" % (len(rows), c["NI"], dt1)}
     return base, {"2mm_D": err}
 
 
@@ -260,9 +303,14 @@ def measure_rows(args, torch, li, synth, timer):
                 fn = lambda: li.li_covariance(M, N, X, Y, mean, out, ws)
             else:
                 fn = lambda: li.li_correlation(M, N, 0.1, X, Y, mean, std, out, ws)
-            ms = timer.time(fn, reps, 1)
-            rows[kind + "_4096x2048"] = {"ms": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
-                                         "frac_fp32_mfma": round(f / ms / 1e9 / PEAK_FP32_MFMA, 4)}
+            st = timer.stats(fn, reps, 1)
+            ms = st["ms"]
+            flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+            ms_cold = timer.time_cold(fn, 10, flush)
+            del flush
+            rows[kind + "_4096x2048"] = dict(st, **{"GFLOP/s": round(f / ms / 1e6, 1),
+                                                   "frac_fp32_mfma": round(f / ms / 1e9 / PEAK_FP32_MFMA, 4),
+                                                   "ms_cold_cache": round(ms_cold, 4)})
             # the same with the centring fused into the contraction's loads
             if kind == "cov":
                 fn = lambda: li.li_covariance_fused(M, N, X, mean, out, ws)
@@ -392,10 +440,17 @@ def measure_matvec(torch, li, synth, timer):
     M = N = 4096
     ws = torch.empty(li.li_matvec_workspace_bytes(M, N) // 4 + 1, device="cuda")
     t, y = torch.empty(M, device="cuda"), torch.empty(N, device="cuda")
-    ms = timer.time(lambda: li.li_atax(M, N, A, vec["x"], t, y, ws), 30, 1)
+    fn = lambda: li.li_atax(M, N, A, vec["x"], t, y, ws)
+    st = timer.stats(fn, 30, 1)
+    ms = st["ms"]
+    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    ms_cold = timer.time_cold(fn, 10, flush)
+    del flush
     b = 4.0 * (M * N + 2 * N + M)
-    out["atax_4096"] = {"ms": round(ms, 4), "GB/s": round(b / ms / 1e6, 1),
-                        "frac_hbm": round(b / ms / 1e6 / PEAK_HBM, 4)}
+    out["atax_4096"] = dict(st, **{"GB/s": round(b / ms / 1e6, 1),
+                                   "frac_hbm": round(b / ms / 1e6 / PEAK_HBM, 4),
+                                   "ms_cold_cache": round(ms_cold, 4),
+                                   "GB/s_cold_cache": round(b / ms_cold / 1e6, 1)})
     del A, ws
     M = N = 16384
     c = synth.matvec_inputs(M, N, seed=9, with_b=True)

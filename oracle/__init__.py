@@ -34,6 +34,7 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     sigs = {
         "orc_num_threads": ([], ctypes.c_int),
+        "orc_set_num_threads": ([ctypes.c_int], None),
         "orc_gemm": ([_i64, _i64, _i64, _dbl, _p, _p, _dbl, _p, _p, _i64, _p], None),
         "orc_mm2": ([_i64, _i64, _i64, _i64, _dbl, _dbl, _p, _p, _p, _p, _p, _i64, _p, _p], None),
         "orc_col_mean": ([_i64, _i64, _p, _p], None),
@@ -82,6 +83,12 @@ def _rows(rows):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the following oracle calls (timing only; results do not
+    depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def gemm(A, B, C0=None, alpha=1.0, beta=0.0, rows=None):

@@ -35,6 +35,17 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads used by the parallel loops that follow (for timing the oracle on
+ * one core); has no effect on results. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * GEMM.  Sec. VI-C (loop internalization): the matrix-multiply work-item
  * kernel accumulates C[i][j] += A[i][k] * B[k][j] over k; Sec. VIII names the
