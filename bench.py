@@ -45,8 +45,10 @@ def syrk_flops(M, N):
 def parse():
     p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=30)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    # enough untimed steps (about 15 ms) for the GPU to leave its idle
+    # clocks before the timed region starts
+    p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--main-only", action="store_true", help="skip the other kernels' rows")
     p.add_argument("--rows-only", action="store_true",
                    help="measure only the rows named by --rows (no headline line)")
