@@ -512,8 +512,13 @@ struct F32Tile {
         __syncthreads();
         Frag f;
         read_frag(As, Bs, 0, wm0, wn0, lane, f);
+        // The loop runs while a third tile remains, so both halves store and
+        // synchronise unconditionally; the last one or two tiles are peeled
+        // below.  (A conditional last step inside the loop makes the
+        // compiler keep two copies of the accumulators and move them
+        // between the two every iteration.)
         int64_t kt = 0;
-        for (; kt + 2 <= nk; kt += 2) {
+        for (; kt + 2 < nk; kt += 2) {
             const int64_t k2 = kbeg + (kt + 2) * BK, k3 = k2 + BK;
             load_a(la, A, lda, M, kend, m0, k2, tid, v4, xr);
             load_b(lb, B, ldb, N, kend, n0, k2, tid, v4, xr);
@@ -530,19 +535,31 @@ struct F32Tile {
             load_a(la1, A, lda, M, kend, m0, k3, tid, v4, xr);
             load_b(lb1, B, ldb, N, kend, n0, k3, tid, v4, xr);
             kloop(As + A_STAGE, Bs + B_STAGE, f, acc, wm0, wn0, lane);
-            if (kt + 2 < nk) {
-                store_a(la, As, tid, xr);
-                store_b(lb, Bs, tid, xr);
-                __syncthreads();
+            store_a(la, As, tid, xr);
+            store_b(lb, Bs, tid, xr);
+            __syncthreads();
+            {
                 Frag g;
                 read_frag(As, Bs, 0, wm0, wn0, lane, g);
                 mma(f, acc);
                 f = g;
-            } else {
-                mma(f, acc);
             }
         }
-        if (kt < nk) {
+        if (kt + 2 == nk) {
+            // tile kt in stage 0, tile kt + 1 in the second register set
+            kloop(As, Bs, f, acc, wm0, wn0, lane);
+            store_a(la1, As + A_STAGE, tid, xr);
+            store_b(lb1, Bs + B_STAGE, tid, xr);
+            __syncthreads();
+            {
+                Frag g;
+                read_frag(As + A_STAGE, Bs + B_STAGE, 0, wm0, wn0, lane, g);
+                mma(f, acc);
+                f = g;
+            }
+            kloop(As + A_STAGE, Bs + B_STAGE, f, acc, wm0, wn0, lane);
+            mma(f, acc);
+        } else {
             kloop(As, Bs, f, acc, wm0, wn0, lane);
             mma(f, acc);
         }
@@ -716,27 +733,147 @@ struct F32Tile {
         __builtin_amdgcn_s_barrier();
         Frag f;
         read_frag_dma(s0, s0 + DMA_A, 0, wm0, wn0, lane, f);
-        for (int64_t kt = 0; kt < nk; ++kt) {
+        // the last tile is peeled so that the loop body is one straight
+        // path (see mainloop_pipelined)
+        for (int64_t kt = 0; kt + 1 < nk; ++kt) {
             // s0: tile kt (being read), s1: tile kt + 1 (in flight), s2: free
             dma_tile(s2, A, lda, B, ldb, M, N, kend, m0, n0, kbeg + (kt + 2) * BK, wave, lane);
             kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
-            if (kt + 1 < nk) {
-                wait_vm_lgkm0<DMA_PER_TILE>();
-                __builtin_amdgcn_s_barrier();
-                Frag g;
-                read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
-                mma(f, acc);
-                f = g;
-            } else {
-                mma(f, acc);
-            }
+            wait_vm_lgkm0<DMA_PER_TILE>();
+            __builtin_amdgcn_s_barrier();
+            Frag g;
+            read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+            mma(f, acc);
+            f = g;
             float *t = s0;
             s0 = s1;
             s1 = s2;
             s2 = t;
         }
+        kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+        mma(f, acc);
         // the loads issued past the end write zeros into the ring; let them
         // land before the LDS is reused or the work-group ends
+        wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();
+    }
+
+    // ------------------------------------------------ PF == 4, whole K-tiles
+    // When [kbeg, kend) is a whole number of K-tiles every tile is read in
+    // full, so the source address of each DMA instruction is computed once
+    // and then advanced by one K-tile per step: no bounds test in the loop.
+    // Rows (columns) past the matrix edge are clamped to the last one; their
+    // products only reach block-tile rows (columns) that are never stored.
+    // The last two K-tiles issue no loads.
+    static constexpr int DMA_A_PER = BM * BK / 256 / NW, DMA_B_PER = BK * BN / 256 / NW;
+
+    template <int TR>
+    __device__ __forceinline__ static void dma_rows_ptrs(const float **p, const float *P,
+                                                         int64_t ld, int64_t rows, int64_t r0,
+                                                         int64_t k0, int wave, int lane)
+    {
+        constexpr int CH = BK / 4, RPI = 64 / CH, INS = TR / RPI;
+#pragma unroll
+        for (int q = 0; q < INS / NW; ++q) {
+            const int ins = wave * (INS / NW) + q;
+            const int row = ins * RPI + lane / CH;
+            const int logical = (lane % CH) ^ swz_rows(row);
+            const int64_t gr = r0 + row < rows ? r0 + row : rows - 1;
+            p[q] = P + gr * ld + k0 + 4 * logical;
+        }
+    }
+
+    template <int W>
+    __device__ __forceinline__ static void dma_kmajor_ptrs(const float **p, const float *P,
+                                                           int64_t ld, int64_t cols, int64_t k0,
+                                                           int64_t x0, int wave, int lane)
+    {
+        constexpr int CH = W / 4, RPI = 64 / CH, INS = BK / RPI;
+#pragma unroll
+        for (int q = 0; q < INS / NW; ++q) {
+            const int ins = wave * (INS / NW) + q;
+            const int k = ins * RPI + lane / CH;
+            const int logical = (lane % CH) ^ swz_k(k);
+            const int64_t gx = x0 + 4 * logical < cols ? x0 + 4 * logical : cols - 4;
+            p[q] = P + (k0 + k) * ld + gx;
+        }
+    }
+
+    // one K-tile of DMA instructions into `stage`; the pointers advance
+    __device__ __forceinline__ static void dma_issue(float *stage, const float **pa,
+                                                     const float **pb, int64_t adv_a,
+                                                     int64_t adv_b, int wave)
+    {
+#pragma unroll
+        for (int q = 0; q < DMA_A_PER; ++q) {
+            lds_dma(pa[q], stage + (wave * DMA_A_PER + q) * 256);
+            pa[q] += adv_a;
+        }
+#pragma unroll
+        for (int q = 0; q < DMA_B_PER; ++q) {
+            lds_dma(pb[q], stage + DMA_A + (wave * DMA_B_PER + q) * 256);
+            pb[q] += adv_b;
+        }
+    }
+
+    __device__ __forceinline__ static void mainloop_dma_full(float *lds, const float *A,
+                                                             int64_t lda, const float *B,
+                                                             int64_t ldb, int64_t M, int64_t N,
+                                                             int64_t kbeg, int64_t m0, int64_t n0,
+                                                             int64_t nk, f32x16 (&acc)[TM][TN])
+    {
+        constexpr int SS = DMA_A + DMA_B;  // floats per stage
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+        const float *pa[DMA_A_PER], *pb[DMA_B_PER];
+        if (A_KMAJOR)
+            dma_kmajor_ptrs<BM>(pa, A, lda, M, kbeg, m0, wave, lane);
+        else
+            dma_rows_ptrs<BM>(pa, A, lda, M, m0, kbeg, wave, lane);
+        if (B_NMAJOR)
+            dma_rows_ptrs<BN>(pb, B, ldb, N, n0, kbeg, wave, lane);
+        else
+            dma_kmajor_ptrs<BN>(pb, B, ldb, N, kbeg, n0, wave, lane);
+        const int64_t adv_a = A_KMAJOR ? BK * lda : BK, adv_b = B_NMAJOR ? BK : BK * ldb;
+        float *s0 = lds, *s1 = lds + SS, *s2 = lds + 2 * SS;
+        dma_issue(s0, pa, pb, adv_a, adv_b, wave);
+        if (nk > 1) {
+            dma_issue(s1, pa, pb, adv_a, adv_b, wave);
+            wait_vm_lgkm0<DMA_PER_TILE>();
+        } else {
+            wait_vm_lgkm0<0>();
+        }
+        __builtin_amdgcn_s_barrier();
+        Frag f;
+        read_frag_dma(s0, s0 + DMA_A, 0, wm0, wn0, lane, f);
+        for (int64_t kt = 0; kt + 2 < nk; ++kt) {
+            // s0: tile kt (being read), s1: tile kt + 1 (in flight), s2: free
+            dma_issue(s2, pa, pb, adv_a, adv_b, wave);
+            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+            wait_vm_lgkm0<DMA_PER_TILE>();
+            __builtin_amdgcn_s_barrier();
+            Frag g;
+            read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+            mma(f, acc);
+            f = g;
+            float *t = s0;
+            s0 = s1;
+            s1 = s2;
+            s2 = t;
+        }
+        if (nk > 1) {
+            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+            wait_vm_lgkm0<0>();
+            __builtin_amdgcn_s_barrier();
+            Frag g;
+            read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+            mma(f, acc);
+            f = g;
+            s0 = s1;
+        }
+        kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+        mma(f, acc);
         wait_vm_lgkm0<0>();
         __builtin_amdgcn_s_barrier();
     }
@@ -760,7 +897,10 @@ struct F32Tile {
         if (nk <= 0) return;
         if (PF == 4) {
             static_assert(PF != 4 || LOAD == kLoadVec4, "direct LDS loads need 16-byte aligned rows");
-            mainloop_dma(lds, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc);
+            if ((kend - kbeg) % BK == 0)
+                mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc);
+            else
+                mainloop_dma(lds, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc);
             return;
         }
         ALoader la;
