@@ -1,11 +1,11 @@
 // Grouped execution: hundreds of independent, uneven GEMM and covariance
 // problems in two launches captured in one HIP graph.
 //
-//  node 1  grouped_stats:    one work-group per (covariance problem, 256
-//                            columns): FP64 column means (same chunking and
-//                            merge order as the single-problem kernels, so
-//                            the results are bitwise the same) and the
-//                            centred data.
+//  node 1  grouped_stats:    one work-group per (covariance problem, 64
+//                            columns), eight threads per column: FP64
+//                            column means (same chunking and merge order as
+//                            the single-problem kernels, so the results are
+//                            bitwise the same) and the centred data.
 //  node 2  grouped_contract: a persistent kernel; work-group b takes the
 //                            output tiles b, b + grid, b + 2*grid, ... of one
 //                            table that lists every tile of every problem
@@ -61,25 +61,35 @@ struct GStatBlock {
 template <int BM, int BN, int BK, int WM, int WN, bool KMAJOR, int LOAD>
 using Tile = F32Tile<BM, BN, BK, WM, WN, KMAJOR, LOAD>;
 
-__global__ __launch_bounds__(kStatThreads) void grouped_stats(const GProb *__restrict__ probs,
-                                                              const GStatBlock *__restrict__ blocks)
+// Statistics of one covariance problem's block of kGStatCols columns: the
+// kMergeGroups thread rows each merge one group of chunk partials (chunk
+// moments and merge order as in the single-problem kernels, so the results
+// are bitwise the same), one thread row merges the group results in order,
+// then every thread row centres a share of the rows.
+constexpr int kGStatCols = 64;
+constexpr int kGStatThreads = kGStatCols * kMergeGroups;
+
+__global__ __launch_bounds__(kGStatThreads) void grouped_stats(const GProb *__restrict__ probs,
+                                                               const GStatBlock *__restrict__ blocks)
 {
+    __shared__ double sn[kMergeGroups][kGStatCols], sm[kMergeGroups][kGStatCols],
+        sq[kMergeGroups][kGStatCols];
+    __shared__ double smean[kGStatCols];
     const GStatBlock b = blocks[blockIdx.x];
     const GProb &p = probs[b.prob];
     const int64_t M = p.M, N = p.N;
-    const int64_t j = (int64_t)b.col0 + threadIdx.x;
-    if (j >= M) return;
+    const int c = threadIdx.x % kGStatCols, g = threadIdx.x / kGStatCols;
+    const int64_t j = (int64_t)b.col0 + c;
+    const bool live = j < M;
     const float *col = p.A + j;
     const int64_t rps = p.rows_per_split, nsplit = p.nsplit;
-    // same two-level merge order as the single-problem finaliser
     const int64_t cpg = chunks_per_group(nsplit);
-    double n = 0.0, ma = 0.0, m2a = 0.0;
-    for (int g = 0; g < kMergeGroups; ++g) {
-        const int64_t s0 = g * cpg, s1 = s0 + cpg < nsplit ? s0 + cpg : nsplit;
-        if (s0 >= s1) continue;
+    const int64_t s0 = g * cpg, s1 = s0 + cpg < nsplit ? s0 + cpg : nsplit;
+    double gn = 0.0, gm = 0.0, gq = 0.0;
+    if (live && s0 < s1) {
         int64_t r0, r1;
         chunk_rows(s0, rps, N, r0, r1);
-        double gn = (double)(r1 - r0), gm, gq;
+        gn = (double)(r1 - r0);
         chunk_moments(col, M, r0, r1, gm, gq);
         for (int64_t s = s0 + 1; s < s1; ++s) {
             chunk_rows(s, rps, N, r0, r1);
@@ -87,17 +97,24 @@ __global__ __launch_bounds__(kStatThreads) void grouped_stats(const GProb *__res
             chunk_moments(col, M, r0, r1, mb, m2b);
             chan_merge(gn, gm, gq, (double)(r1 - r0), mb, m2b);
         }
-        if (g == 0) {
-            n = gn;
-            ma = gm;
-            m2a = gq;
-        } else {
-            chan_merge(n, ma, m2a, gn, gm, gq);
-        }
     }
-    p.mean[j] = ma;
+    sn[g][c] = gn;
+    sm[g][c] = gm;
+    sq[g][c] = gq;
+    __syncthreads();
+    if (g == 0) {
+        // group 0 always holds chunk 0; empty groups (gn == 0) are skipped
+        double n = sn[0][c], ma = sm[0][c], m2a = sq[0][c];
+        for (int h = 1; h < kMergeGroups; ++h)
+            if (sn[h][c] > 0.0) chan_merge(n, ma, m2a, sn[h][c], sm[h][c], sq[h][c]);
+        if (live) p.mean[j] = ma;
+        smean[c] = ma;
+    }
+    __syncthreads();
+    if (!live) return;
+    const double ma = smean[c];
     float *ycol = p.Y + j;
-    for (int64_t r = 0; r < N; ++r) ycol[r * M] = centre_value(col[r * M], ma, 0.0, false);
+    for (int64_t r = g; r < N; r += kMergeGroups) ycol[r * M] = centre_value(col[r * M], ma, 0.0, false);
 }
 
 template <class T>
@@ -358,7 +375,7 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
                 const StatsPlan sp = stats_plan(q.M, q.N);
                 g.rows_per_split = sp.rows_per_split;
                 g.nsplit = sp.nsplit;
-                for (int64_t c0 = 0; c0 < q.M; c0 += kStatThreads) stat.push_back({i, (int32_t)c0});
+                for (int64_t c0 = 0; c0 < q.M; c0 += kGStatCols) stat.push_back({i, (int32_t)c0});
                 loop_ws = std::max(loop_ws, stats_workspace_bytes(q.M, q.N));
                 const int tm = (int)((q.M + bt - 1) / bt);
                 const double w = (double)bt * bt * ((double)q.N + 1.0);
@@ -419,7 +436,7 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
         hipKernelNodeParams kp{};
         kp.func = (void *)grouped_stats;
         kp.gridDim = dim3((unsigned)p->nstat);
-        kp.blockDim = dim3(kStatThreads);
+        kp.blockDim = dim3(kGStatThreads);
         kp.sharedMemBytes = 0;
         kp.kernelParams = args;
         kp.extra = nullptr;

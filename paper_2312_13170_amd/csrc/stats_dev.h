@@ -20,19 +20,16 @@ __device__ __forceinline__ void chunk_moments(const float *col, int64_t ld, int6
     const double x0 = (double)col[r0 * ld];
     double s1 = 0.0, s2 = 0.0;
     int64_t r = r0;
-    for (; r + 4 <= r1; r += 4) {
-        const double d0 = (double)col[(r + 0) * ld] - x0;
-        const double d1 = (double)col[(r + 1) * ld] - x0;
-        const double d2 = (double)col[(r + 2) * ld] - x0;
-        const double d3 = (double)col[(r + 3) * ld] - x0;
-        s1 += d0;
-        s2 += d0 * d0;
-        s1 += d1;
-        s2 += d1 * d1;
-        s1 += d2;
-        s2 += d2 * d2;
-        s1 += d3;
-        s2 += d3 * d3;
+    // eight loads in flight, then the additions in row order
+    for (; r + 8 <= r1; r += 8) {
+        double d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = (double)col[(r + u) * ld] - x0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            s1 += d[u];
+            s2 += d[u] * d[u];
+        }
     }
     for (; r < r1; ++r) {
         const double d = (double)col[r * ld] - x0;
