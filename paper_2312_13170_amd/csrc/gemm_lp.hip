@@ -20,9 +20,11 @@
 //
 // LDS rows are BK elements (64 or 128 bytes, i.e. CPR 16-byte chunks).  The
 // chunk index is XOR-swizzled with the row so that the 16-byte reads of 16
-// consecutive rows at one logical chunk fall into distinct bank groups:
+// consecutive rows at one logical chunk fall into distinct bank groups, and
+// so do the 16-byte stores of consecutive chunks (both measured free of bank
+// conflicts with the hardware counter):
 //   CPR = 8: phys = c ^ ((r ^ (r >> 3)) & 7)
-//   CPR = 4: phys = c ^ (((r >> 1) ^ (r >> 3)) & 3)
+//   CPR = 4: phys = c ^ ((r >> 2) & 3)
 #include <hip/hip_runtime.h>
 
 #include "li_internal.h"
@@ -174,7 +176,7 @@ template <int CPR>
 __device__ __forceinline__ int swz(int r, int c)
 {
     if (CPR == 8) return c ^ ((r ^ (r >> 3)) & 7);
-    return c ^ (((r >> 1) ^ (r >> 3)) & 3);
+    return c ^ ((r >> 2) & 3);
 }
 
 // LAYOUT 1: rows of BK elements with XOR-swizzled 16-byte chunks;
