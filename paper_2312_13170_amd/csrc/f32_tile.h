@@ -277,8 +277,8 @@ struct F32Tile {
     // raw data, centred (1) or normalised (2) column by column on their way
     // into LDS (the statistics kernels' transform, fused into the loads).
     static constexpr int XFORM = XFORM_;
-    static_assert(XFORM == 0 || (A_KMAJOR && !B_NMAJOR && PF != 4),
-                  "fused centring needs k-major operands loaded through registers");
+    static_assert(XFORM == 0 || (A_KMAJOR && !B_NMAJOR),
+                  "fused centring needs k-major operands");
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
@@ -315,8 +315,13 @@ struct F32Tile {
     // d_a sum_i y_ib + d_b sum_i y_ia + n d_a d_b, where the sums of centred
     // values vanish, so the contraction changes by about n d_a d_b:
     // far below FP32 rounding of the result.
+    // With PF == 4 the transform is applied to the matrix-core operands
+    // after the LDS reads instead (same FP32 operations): rma / rfa hold the
+    // statistics of the A columns this lane reads (one per 32-column block
+    // tm), rmb / rfb those of its B columns.
     struct XRegs {
         f32x4 ma, fa, mb, fb;
+        float rma[TM], rfa[TM], rmb[TN], rfb[TN];
     };
 
     __device__ __forceinline__ static void load_xregs(XRegs &x, const double *mean,
@@ -331,6 +336,21 @@ struct F32Tile {
             x.mb[e] = cb + e < N ? (float)mean[cb + e] : 0.f;
             x.fa[e] = XFORM == 2 && ca + e < M ? (float)factor[ca + e] : 0.f;
             x.fb[e] = XFORM == 2 && cb + e < N ? (float)factor[cb + e] : 0.f;
+        }
+        const int lane = tid & 63, wave = tid >> 6;
+        const int64_t wa = m0 + (wave / WN) * (BM / WM) + (lane & 31);
+        const int64_t wb = n0 + (wave % WN) * (BN / WN) + (lane & 31);
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+            const int64_t c = wa + 32 * t;
+            x.rma[t] = c < M ? (float)mean[c] : 0.f;
+            x.rfa[t] = XFORM == 2 && c < M ? (float)factor[c] : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+            const int64_t c = wb + 32 * t;
+            x.rmb[t] = c < N ? (float)mean[c] : 0.f;
+            x.rfb[t] = XFORM == 2 && c < N ? (float)factor[c] : 0.f;
         }
     }
 
@@ -703,14 +723,36 @@ struct F32Tile {
         }
     }
 
+    // the column transform of XFORM on operands read from LDS
+    __device__ __forceinline__ static void xform_frag(Frag &f, const XRegs *x)
+    {
+        if constexpr (XFORM != 0) {
+#pragma unroll
+            for (int t = 0; t < TM; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    f.a[t][s] = f.a[t][s] - x->rma[t];
+                    if (XFORM == 2) f.a[t][s] *= x->rfa[t];
+                }
+#pragma unroll
+            for (int t = 0; t < TN; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    f.b[t][s] = f.b[t][s] - x->rmb[t];
+                    if (XFORM == 2) f.b[t][s] *= x->rfb[t];
+                }
+        }
+    }
+
     __device__ __forceinline__ static void kloop_dma(const float *As, const float *Bs, Frag &f,
                                                      f32x16 (&acc)[TM][TN], int wm0, int wn0,
-                                                     int lane)
+                                                     int lane, const XRegs *xr = nullptr)
     {
 #pragma unroll
         for (int kk = 8; kk < BK; kk += 8) {
             Frag g;
             read_frag_dma(As, Bs, kk, wm0, wn0, lane, g);
+            xform_frag(g, xr);
             mma(f, acc);
             f = g;
         }
@@ -820,7 +862,8 @@ struct F32Tile {
                                                              int64_t lda, const float *B,
                                                              int64_t ldb, int64_t M, int64_t N,
                                                              int64_t kbeg, int64_t m0, int64_t n0,
-                                                             int64_t nk, f32x16 (&acc)[TM][TN])
+                                                             int64_t nk, f32x16 (&acc)[TM][TN],
+                                                             const XRegs *xr)
     {
         constexpr int SS = DMA_A + DMA_B;  // floats per stage
         const int lane = threadIdx.x & 63;
@@ -847,14 +890,16 @@ struct F32Tile {
         __builtin_amdgcn_s_barrier();
         Frag f;
         read_frag_dma(s0, s0 + DMA_A, 0, wm0, wn0, lane, f);
+        xform_frag(f, xr);
         for (int64_t kt = 0; kt + 2 < nk; ++kt) {
             // s0: tile kt (being read), s1: tile kt + 1 (in flight), s2: free
             dma_issue(s2, pa, pb, adv_a, adv_b, wave);
-            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane, xr);
             wait_vm_lgkm0<DMA_PER_TILE>();
             __builtin_amdgcn_s_barrier();
             Frag g;
             read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+            xform_frag(g, xr);
             mma(f, acc);
             f = g;
             float *t = s0;
@@ -863,16 +908,17 @@ struct F32Tile {
             s2 = t;
         }
         if (nk > 1) {
-            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane, xr);
             wait_vm_lgkm0<0>();
             __builtin_amdgcn_s_barrier();
             Frag g;
             read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+            xform_frag(g, xr);
             mma(f, acc);
             f = g;
             s0 = s1;
         }
-        kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane);
+        kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane, xr);
         mma(f, acc);
         wait_vm_lgkm0<0>();
         __builtin_amdgcn_s_barrier();
@@ -888,21 +934,38 @@ struct F32Tile {
                                                     int64_t m0, int64_t n0, f32x16 (&acc)[TM][TN],
                                                     bool v4 = true, const XRegs *xr = nullptr)
     {
+        const int64_t nk = (kend - kbeg + BK - 1) / BK;
+        if (nk <= 0) return;
+        if constexpr (PF == 4) {
+            static_assert(LOAD == kLoadVec4, "direct LDS loads need 16-byte aligned rows");
+            if constexpr (XFORM != 0) {
+                // Launched only on K ranges of whole K-tiles (out-of-range k
+                // would not become 0 after the transform); a ragged range
+                // would be skipped rather than read past the matrix.
+                if ((kend - kbeg) % BK == 0)
+                    mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
+            } else if ((kend - kbeg) % BK == 0) {
+                mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
+            } else {
+                mainloop_dma(lds, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc);
+            }
+        } else {
+            mainloop_regs(lds, lds + 2 * A_STAGE, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc,
+                          v4, xr);
+        }
+    }
+
+    // Register-staged main loops (PF 1 to 3).
+    __device__ __forceinline__ static void mainloop_regs(float *As, float *Bs, const float *A,
+                                                         int64_t lda, const float *B, int64_t ldb,
+                                                         int64_t M, int64_t N, int64_t kbeg,
+                                                         int64_t kend, int64_t m0, int64_t n0,
+                                                         int64_t nk, f32x16 (&acc)[TM][TN],
+                                                         bool v4, const XRegs *xr)
+    {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
-        float *As = lds;
-        float *Bs = lds + 2 * A_STAGE;
-        const int64_t nk = (kend - kbeg + BK - 1) / BK;
-        if (nk <= 0) return;
-        if (PF == 4) {
-            static_assert(PF != 4 || LOAD == kLoadVec4, "direct LDS loads need 16-byte aligned rows");
-            if ((kend - kbeg) % BK == 0)
-                mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc);
-            else
-                mainloop_dma(lds, A, lda, B, ldb, M, N, kbeg, kend, m0, n0, nk, acc);
-            return;
-        }
         ALoader la;
         BLoader lb;
         load_a(la, A, lda, M, kend, m0, kbeg, tid, v4, xr);
