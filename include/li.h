@@ -283,7 +283,10 @@ typedef struct li_tile_config {
                                across the barrier; 4: direct HBM-to-LDS
                                loads into a three-stage ring); FP32 GEMM
                                5-7: modes 1-3 with B transposed into LDS
-                               so both operands take 16-byte LDS reads */
+                               so both operands take 16-byte LDS reads;
+                               8: direct HBM-to-LDS loads into a two-stage
+                               ring (mode 2 when K is not a multiple of
+                               the K-tile) */
 } li_tile_config;
 
 int32_t li_tune_num_candidates(int32_t kernel);

@@ -272,7 +272,9 @@ struct F32Tile {
                   "the transposing B loader is for row-major B through registers");
     // B is k-contiguous in LDS
     static constexpr bool BT = B_NMAJOR || B_LDST;
-    static_assert(PF >= 1 && PF <= 4, "prefetch mode is 1 to 4");
+    static_assert((PF >= 1 && PF <= 4) || PF == 8, "prefetch mode is 1 to 4 or 8");
+    // direct HBM-to-LDS loads: a ring of three stages (PF 4) or two (PF 8)
+    static constexpr bool DMA = PF == 4 || PF == 8;
     // XFORM: 0 operands used as loaded; 1 / 2: both k-major operands are
     // raw data, centred (1) or normalised (2) column by column on their way
     // into LDS (the statistics kernels' transform, fused into the loads).
@@ -295,7 +297,8 @@ struct F32Tile {
     // PF == 4 keeps three unpadded, XOR-swizzled stages filled by direct
     // HBM-to-LDS loads (see mainloop_dma).
     static constexpr int DMA_A = BM * BK, DMA_B = BK * BN;
-    static constexpr int LDS_FLOATS = PF == 4 ? 3 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
+    static constexpr int LDS_FLOATS =
+        PF == 4 ? 3 * (DMA_A + DMA_B) : PF == 8 ? 2 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
     // transposing loads in 4 x 4 blocks when there are enough blocks for
@@ -610,7 +613,7 @@ struct F32Tile {
     __device__ __forceinline__ static int swz_k(int k) { return ((k >> 2) & 1) << 3; }
 
     __device__ __forceinline__ static const float *zero16() { return zero_src(); }
-    static_assert(PF != 4 || BK == 32 || BK == 64, "direct LDS loads use K-tiles of 32 or 64");
+    static_assert(!DMA || BK == 32 || BK == 64, "direct LDS loads use K-tiles of 32 or 64");
 
     __device__ __forceinline__ static void lds_dma(const float *src, float *dst)
     {
@@ -881,6 +884,34 @@ struct F32Tile {
         const int64_t adv_a = A_KMAJOR ? BK * lda : BK, adv_b = B_NMAJOR ? BK : BK * ldb;
         float *s0 = lds, *s1 = lds + SS, *s2 = lds + 2 * SS;
         dma_issue(s0, pa, pb, adv_a, adv_b, wave);
+        if constexpr (PF == 8) {
+            // two stages: tile kt + 1 is loaded while tile kt is multiplied
+            wait_vm_lgkm0<0>();
+            __builtin_amdgcn_s_barrier();
+            Frag f;
+            read_frag_dma(s0, s0 + DMA_A, 0, wm0, wn0, lane, f);
+            xform_frag(f, xr);
+            for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+                // s1 held tile kt - 1, whose reads all ended before the
+                // last barrier
+                dma_issue(s1, pa, pb, adv_a, adv_b, wave);
+                kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane, xr);
+                wait_vm_lgkm0<0>();
+                __builtin_amdgcn_s_barrier();
+                Frag g;
+                read_frag_dma(s1, s1 + DMA_A, 0, wm0, wn0, lane, g);
+                xform_frag(g, xr);
+                mma(f, acc);
+                f = g;
+                float *t = s0;
+                s0 = s1;
+                s1 = t;
+            }
+            kloop_dma(s0, s0 + DMA_A, f, acc, wm0, wn0, lane, xr);
+            mma(f, acc);
+            __builtin_amdgcn_s_barrier();
+            return;
+        }
         if (nk > 1) {
             dma_issue(s1, pa, pb, adv_a, adv_b, wave);
             wait_vm_lgkm0<DMA_PER_TILE>();
@@ -936,12 +967,13 @@ struct F32Tile {
     {
         const int64_t nk = (kend - kbeg + BK - 1) / BK;
         if (nk <= 0) return;
-        if constexpr (PF == 4) {
+        if constexpr (DMA) {
             static_assert(LOAD == kLoadVec4, "direct LDS loads need 16-byte aligned rows");
-            if constexpr (XFORM != 0) {
-                // Launched only on K ranges of whole K-tiles (out-of-range k
-                // would not become 0 after the transform); a ragged range
-                // would be skipped rather than read past the matrix.
+            if constexpr (XFORM != 0 || PF == 8) {
+                // Launched only on K ranges of whole K-tiles (the two-stage
+                // ring has no ragged-tile loop, and out-of-range k would not
+                // become 0 after the transform); a ragged range would be
+                // skipped rather than read past the matrix.
                 if ((kend - kbeg) % BK == 0)
                     mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
             } else if ((kend - kbeg) % BK == 0) {

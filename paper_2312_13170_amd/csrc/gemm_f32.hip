@@ -58,16 +58,21 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
     const bool v4 = (alpha == 0.f || (K % 4 == 0 && N % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0 &&
                                       aligned16(A) && aligned16(B)));
     switch (cfg) {
-// prefetch modes 5-7 are modes 1-3 with B transposed into LDS; mode 4
-// (direct-to-LDS) needs 16-byte rows and falls back to mode 2 otherwise
+// prefetch modes 5-7 are modes 1-3 with B transposed into LDS; the
+// direct-to-LDS modes (4: three-stage ring, 8: two-stage ring) need 16-byte
+// rows and fall back to mode 2 otherwise, mode 8 also when K is not a
+// multiple of the K-tile
 #define LI_T(BM, BN, BK, WM, WN, LOAD, PF) \
-    F32Tile<BM, BN, BK, WM, WN, false, LOAD, (PF > 4 ? PF - 4 : PF), false, 0, (PF > 4)>
+    F32Tile<BM, BN, BK, WM, WN, false, LOAD, (PF > 4 && PF < 8 ? PF - 4 : PF), false, 0, (PF > 4 && PF < 8)>
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                     \
     case IDX:                                                                                      \
-        return v4 ? run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadVec4, PF)>(M, N, K, alpha, A, lda, B, ldb, \
-                                                                   beta, C, ldc, s)                \
-                  : run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadScalar, (PF == 4 ? 2 : PF))>(            \
-                        M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+        return v4 && (PF != 8 || K % BK == 0)                                                      \
+                   ? run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadVec4, PF)>(M, N, K, alpha, A, lda, B, ldb, \
+                                                                      beta, C, ldc, s)             \
+                   : v4 ? run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadVec4, (PF == 8 ? 2 : PF))>(       \
+                              M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s)                     \
+                        : run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadScalar, (PF == 4 || PF == 8 ? 2 : PF))>( \
+                              M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
         LI_GEMM_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
 #undef LI_T

@@ -92,10 +92,14 @@ def test_config0(li, orc):
 
 
 @pytest.mark.parametrize("shape", [(515, 387, 301), (1000, 1030, 260), (129, 1100, 67),
-                                   (516, 388, 300), (260, 132, 1028)])
+                                   (516, 388, 300), (260, 132, 1028), (260, 132, 1024),
+                                   (129, 516, 192)])
 def test_every_tile_shape(li, orc, shape):
-    # the last two shapes have K and N multiples of 4 (vector and direct-to-LDS
-    # loads) with ragged tiles in M, N and K
+    # (516, 388, 300) and (260, 132, 1028) have K and N multiples of 4
+    # (vector and direct-to-LDS loads) with ragged tiles in M, N and K; the
+    # last two have K a multiple of 64 (whole K-tiles: the direct-to-LDS
+    # loops with precomputed source pointers and the two-stage ring) with
+    # ragged M and N
     M, N, K = shape
     A = synth.uniform_pm1(34, "A", (M, K))
     B = synth.uniform_pm1(34, "B", (K, N))
