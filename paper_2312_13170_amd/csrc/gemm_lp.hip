@@ -27,6 +27,8 @@
 //   CPR = 4: phys = c ^ ((r >> 2) & 3)
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "li_internal.h"
 #include "tiles.h"
 
@@ -180,7 +182,9 @@ __device__ __forceinline__ int swz(int r, int c)
 }
 
 // LAYOUT 1: rows of BK elements with XOR-swizzled 16-byte chunks;
-// LAYOUT 2: rows padded by 16 bytes, chunks in place.
+// LAYOUT 2: rows padded by 16 bytes, chunks in place;
+// LAYOUT 3: LAYOUT 1 filled by direct HBM-to-LDS loads into a ring of
+// stages (gemm_lp_dma_kernel).
 template <int BM_, int BN_, int BK_, int WM_, int WN_, int TERMS, bool FP16, int LAYOUT = 1>
 struct LpTile {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
@@ -190,8 +194,9 @@ struct LpTile {
     static constexpr int PARTS = TERMS == 3 ? 2 : 1;
     static constexpr int NTERMS = TERMS;
     static constexpr bool IS_FP16 = FP16;
+    static constexpr int LAYOUT_ID = LAYOUT;
     static constexpr int RS = LAYOUT == 2 ? BK + 8 : BK;  // LDS row stride (elements)
-    static_assert(LAYOUT == 1 || LAYOUT == 2, "unknown LDS layout");
+    static_assert(LAYOUT >= 1 && LAYOUT <= 3, "unknown LDS layout");
     // element offset of 16-byte chunk c of row r
     __device__ __forceinline__ static int off(int r, int c)
     {
@@ -358,6 +363,226 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restri
         }
 }
 
+// One K-tile of matrix-core steps on a stage in LDS (layout 1 / 3).
+template <class T>
+__device__ __forceinline__ void lp_tile_mma(const uint16_t *As, const uint16_t *Bs,
+                                            f32x16 (&acc)[T::TM][T::TN], int wm0, int wn0,
+                                            int l32, int hsel)
+{
+    constexpr int TM = T::TM, TN = T::TN, PARTS = T::PARTS;
+#pragma unroll
+    for (int kk = 0; kk < T::BK; kk += 16) {
+        const int cidx = kk / 8 + hsel;
+        u32x4 fa[PARTS][TM], fb[PARTS][TN];
+#pragma unroll
+        for (int p = 0; p < PARTS; ++p) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                fa[p][i] = *reinterpret_cast<const u32x4 *>(As + p * T::A_ELEMS +
+                                                            T::off(wm0 + 32 * i + l32, cidx));
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                fb[p][j] = *reinterpret_cast<const u32x4 *>(Bs + p * T::B_ELEMS +
+                                                            T::off(wn0 + 32 * j + l32, cidx));
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if (T::IS_FP16) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8, fa[0][i]), __builtin_bit_cast(f16x8, fb[0][j]),
+                        acc[i][j], 0, 0, 0);
+                } else {
+                    if (T::NTERMS == 3) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, fa[1][i]), __builtin_bit_cast(bf16x8, fb[0][j]),
+                            acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, fa[0][i]), __builtin_bit_cast(bf16x8, fb[PARTS - 1][j]),
+                            acc[i][j], 0, 0, 0);
+                    }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, fa[0][i]), __builtin_bit_cast(bf16x8, fb[0][j]),
+                        acc[i][j], 0, 0, 0);
+                }
+            }
+    }
+}
+
+// s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 encoding)
+template <int VM>
+__device__ __forceinline__ void lp_wait_vm_lgkm0()
+{
+    static_assert(VM >= 0 && VM < 64, "vmcnt out of range");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (0 << 8));
+}
+
+// One K-tile of this wave's direct loads into `stage` (see
+// gemm_lp_dma_kernel); the sources advance by one K-tile.
+template <class T, int AW, int BW>
+__device__ __forceinline__ void lp_issue(uint16_t *stage, const uint16_t *(&pa)[T::PARTS][AW],
+                                         const uint16_t *(&pb)[T::PARTS][BW], int wave)
+{
+#pragma unroll
+    for (int p = 0; p < T::PARTS; ++p) {
+#pragma unroll
+        for (int q = 0; q < AW; ++q) {
+            __builtin_amdgcn_global_load_lds(
+                pa[p][q],
+                (__attribute__((address_space(3))) void *)(stage + p * T::A_ELEMS + (wave * AW + q) * 512),
+                16, 0, 0);
+            pa[p][q] += T::BK;
+        }
+#pragma unroll
+        for (int q = 0; q < BW; ++q) {
+            __builtin_amdgcn_global_load_lds(
+                pb[p][q],
+                (__attribute__((address_space(3))) void *)(stage + T::PARTS * T::A_ELEMS +
+                                                           p * T::B_ELEMS + (wave * BW + q) * 512),
+                16, 0, 0);
+            pb[p][q] += T::BK;
+        }
+    }
+}
+
+// Direct HBM-to-LDS variant (LAYOUT 3).  The padded operands need no bounds
+// checks, so each wave's load sources are computed once and advanced by
+// one K-tile per step.  One global_load_lds_dwordx4 of a wave fills one
+// kilobyte of a stage (64 / CPR rows of the K-tile): lane i writes physical
+// chunk i % CPR of row i / CPR, so it fetches the logical chunk that the
+// layout-1 swizzle places there.  Ring of three stages when they fit in
+// LDS, else two (64-wide K-tiles, or the split variant whose stage holds
+// both parts); one barrier per K-tile after an explicit wait for the next
+// tile; the last tiles are peeled so the loop body is one straight path.
+template <class T>
+__global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__restrict__ Ah,
+                                                            const uint16_t *__restrict__ Al,
+                                                            const uint16_t *__restrict__ Bh,
+                                                            const uint16_t *__restrict__ Bl,
+                                                            int64_t Kp, float *__restrict__ C,
+                                                            int64_t M, int64_t N, float alpha,
+                                                            float beta, int tiles_m, int tiles_n,
+                                                            int group_m)
+{
+    constexpr int BM = T::BM, BN = T::BN, BK = T::BK, CPR = T::CPR;
+    constexpr int TM = T::TM, TN = T::TN, PARTS = T::PARTS;
+    constexpr int NW = T::NT / 64;
+    // ring stages: three when they fit in LDS, else two
+    constexpr int ST = 3 * T::STAGE * 2 <= 160 * 1024 ? 3 : 2;
+    constexpr int RPI = 64 / CPR;  // rows one load instruction fills
+    constexpr int A_INS = BM / RPI, B_INS = BN / RPI;  // instructions per part and tile
+    static_assert(A_INS % NW == 0 && B_INS % NW == 0, "load instructions must divide among waves");
+    constexpr int AW = A_INS / NW, BW = B_INS / NW;
+    constexpr int PER_TILE = PARTS * (AW + BW);  // instructions of one wave per K-tile
+    __shared__ __attribute__((aligned(16))) uint16_t lds[ST * T::STAGE];
+
+    const int nb = tiles_m * tiles_n;
+    const int t = xcd_remap_lp(blockIdx.x, nb);
+    const int per_group = group_m * tiles_n;
+    const int g = t / per_group;
+    const int first = g * group_m;
+    const int gm = min(group_m, tiles_m - first);
+    const int in = t - g * per_group;
+    const int tmi = first + in % gm, tni = in / gm;
+    const int64_t m0 = (int64_t)tmi * BM, n0 = (int64_t)tni * BN;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm0 = (wave / T::WN) * (BM / T::WM), wn0 = (wave % T::WN) * (BN / T::WN);
+    const int l32 = lane & 31, hsel = lane >> 5;
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    // source of each of this wave's load instructions at k = 0
+    const uint16_t *srcA[2] = {Ah + m0 * Kp, Al ? Al + m0 * Kp : nullptr};
+    const uint16_t *srcB[2] = {Bh + n0 * Kp, Bl ? Bl + n0 * Kp : nullptr};
+    const uint16_t *pa[PARTS][AW], *pb[PARTS][BW];
+    const int rr = lane / CPR, pc = lane % CPR;
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p) {
+#pragma unroll
+        for (int q = 0; q < AW; ++q) {
+            const int r = (wave * AW + q) * RPI + rr;
+            pa[p][q] = srcA[p] + (int64_t)r * Kp + swz<CPR>(r, pc) * 8;
+        }
+#pragma unroll
+        for (int q = 0; q < BW; ++q) {
+            const int r = (wave * BW + q) * RPI + rr;
+            pb[p][q] = srcB[p] + (int64_t)r * Kp + swz<CPR>(r, pc) * 8;
+        }
+    }
+    const int64_t nk = Kp / BK;
+    uint16_t *s0 = lds, *s1 = lds + T::STAGE, *s2 = lds + (ST - 1) * T::STAGE;
+    lp_issue<T, AW, BW>(s0, pa, pb, wave);
+    if constexpr (ST == 3) {
+        if (nk > 1) {
+            lp_issue<T, AW, BW>(s1, pa, pb, wave);
+            lp_wait_vm_lgkm0<PER_TILE>();
+        } else {
+            lp_wait_vm_lgkm0<0>();
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt + 2 < nk; ++kt) {
+            // s0: tile kt, s1: tile kt + 1 (in flight), s2: free
+            lp_issue<T, AW, BW>(s2, pa, pb, wave);
+            lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
+            lp_wait_vm_lgkm0<PER_TILE>();
+            __builtin_amdgcn_s_barrier();
+            uint16_t *x = s0;
+            s0 = s1;
+            s1 = s2;
+            s2 = x;
+        }
+        if (nk > 1) {
+            lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
+            lp_wait_vm_lgkm0<0>();
+            __builtin_amdgcn_s_barrier();
+            s0 = s1;
+        }
+        lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
+    } else {
+        lp_wait_vm_lgkm0<0>();
+        __syncthreads();
+        for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+            // s1 held tile kt - 1, whose reads ended before the last barrier
+            lp_issue<T, AW, BW>(s1, pa, pb, wave);
+            lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
+            lp_wait_vm_lgkm0<0>();
+            __builtin_amdgcn_s_barrier();
+            uint16_t *x = s0;
+            s0 = s1;
+            s1 = x;
+        }
+        lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
+        (void)s2;
+    }
+
+    // C = alpha*acc + beta*C over the in-range part of the tile.
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t col = n0 + wn0 + 32 * j + l32;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = m0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                if (row < M && col < N) {
+                    float *c = C + row * N + col;
+                    float r = alpha * acc[i][j][v];
+                    if (beta != 0.f) r += beta * *c;
+                    *c = r;
+                }
+            }
+        }
+}
+
 struct LpLayout {
     int64_t Mp, Np, Kp;
     uint16_t *Ah, *Al, *Bh, *Bl;
@@ -384,14 +609,31 @@ LpLayout lp_layout(int64_t M, int64_t N, int64_t K, int prec, void *ws)
     return L;
 }
 
+// one overload per kernel (register-staged / direct-to-LDS layouts)
+template <class T>
+void launch_lp_tiles(std::false_type, const LpLayout &L, int64_t M, int64_t N, float alpha,
+                     float beta, float *C, int tiles_m, int tiles_n, hipStream_t s)
+{
+    hipLaunchKernelGGL(gemm_lp_kernel<T>, dim3(tiles_m * tiles_n), dim3(T::NT), 0, s, L.Ah, L.Al,
+                       L.Bh, L.Bl, L.Kp, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
+}
+
+template <class T>
+void launch_lp_tiles(std::true_type, const LpLayout &L, int64_t M, int64_t N, float alpha,
+                     float beta, float *C, int tiles_m, int tiles_n, hipStream_t s)
+{
+    hipLaunchKernelGGL(gemm_lp_dma_kernel<T>, dim3(tiles_m * tiles_n), dim3(T::NT), 0, s, L.Ah,
+                       L.Al, L.Bh, L.Bl, L.Kp, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
+}
+
 template <class T>
 int run_lp(const LpLayout &L, int64_t M, int64_t N, float alpha, float beta, float *C,
            hipStream_t s)
 {
     const int tiles_m = (int)((M + T::BM - 1) / T::BM);
     const int tiles_n = (int)((N + T::BN - 1) / T::BN);
-    hipLaunchKernelGGL(gemm_lp_kernel<T>, dim3(tiles_m * tiles_n), dim3(T::NT), 0, s, L.Ah, L.Al,
-                       L.Bh, L.Bl, L.Kp, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
+    launch_lp_tiles<T>(std::integral_constant<bool, T::LAYOUT_ID == 3>{}, L, M, N, alpha, beta, C,
+                       tiles_m, tiles_n, s);
     return (int)hipGetLastError();
 }
 
