@@ -132,17 +132,34 @@ __global__ __launch_bounds__(256) void round_rows_kernel(const float *__restrict
 __global__ __launch_bounds__(256) void round_transpose_kernel(const float *__restrict__ B,
                                                               int64_t K, int64_t N, int64_t Np,
                                                               int64_t Kp, uint16_t *__restrict__ hi,
-                                                              uint16_t *__restrict__ lo, int prec)
+                                                              uint16_t *__restrict__ lo, int prec,
+                                                              int vec4)
 {
     __shared__ float t[64][65];
     const int64_t n0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 64;
     const int tid = threadIdx.x;
+    if (vec4) {
+        // 16-byte loads (N a multiple of 4, B 16-byte aligned): four per thread
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = tid + i * 256;
-        const int kr = e / 64, nc = e % 64;
-        const int64_t gk = k0 + kr, gn = n0 + nc;
-        t[kr][nc] = (gk < K && gn < N) ? B[gk * N + gn] : 0.f;
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * 256;
+            const int kr = e / 16, nc = (e % 16) * 4;
+            const int64_t gk = k0 + kr, gn = n0 + nc;
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            if (gk < K && gn < N) v = *reinterpret_cast<const f32x4 *>(B + gk * N + gn);
+            t[kr][nc] = v[0];
+            t[kr][nc + 1] = v[1];
+            t[kr][nc + 2] = v[2];
+            t[kr][nc + 3] = v[3];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + i * 256;
+            const int kr = e / 64, nc = e % 64;
+            const int64_t gk = k0 + kr, gn = n0 + nc;
+            t[kr][nc] = (gk < K && gn < N) ? B[gk * N + gn] : 0.f;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -669,8 +686,9 @@ int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alp
                            L.Kp, L.Ah, L.Al, prec, vec4);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
+        const int bvec4 = (N % 4 == 0) && (((uintptr_t)B & 15) == 0);
         hipLaunchKernelGGL(round_transpose_kernel, dim3((unsigned)(L.Np / 64), (unsigned)(L.Kp / 64)),
-                           dim3(256), 0, s, B, K, N, L.Np, L.Kp, L.Bh, L.Bl, prec);
+                           dim3(256), 0, s, B, K, N, L.Np, L.Kp, L.Bh, L.Bl, prec, bvec4);
         e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
     }
