@@ -11,8 +11,9 @@
 //
 // Work decomposition: a work-group of 256 threads owns a slab of
 // 1024 * NCH columns (thread t holds the float4 chunks at columns
-// slab + 4 * (c * 256 + t), c < NCH, so each row load is coalesced) and a
-// contiguous group of rows, RB rows per step.  Per step:
+// slab + 4 * (c * 256 + t), c < NCH, so each row load is coalesced) and
+// every G-th block of RB rows (G work-groups per slab), one block per step.
+// Per step:
 //   * each row's dot product with u is reduced across the wave (xor
 //     butterfly: every lane ends with the same value) and across the four
 //     waves through LDS in fixed wave order (double-buffered, one barrier);
@@ -20,7 +21,7 @@
 // atax needs w_i = d_i, the finished dot product of the same row: when the
 // whole row fits one slab (N <= 16384) the row is still in registers when
 // d_i is known, so A is read once.  Wider rows take two passes.
-// Column partials (one row of floats per row group) and, with several
+// Column partials (one row of floats per work-group) and, with several
 // slabs, row partials (one per slab) go to a workspace; finish kernels add
 // them in fixed order, so every result is deterministic.
 #include <hip/hip_runtime.h>
@@ -51,7 +52,6 @@ struct MvArgs {
     float alpha, beta;   // gesummv
     float *row_part;     // slabs > 1: [2][slabs][M] row partials (A, B)
     float *col_part;     // [groups][N] column partials
-    int64_t rows_per;    // rows per row group
     int vec;             // 16-byte matrix loads (N % 4 == 0, aligned rows)
     int vec_part;        // 16-byte partial stores (also an aligned workspace)
 };
@@ -130,15 +130,21 @@ __global__ __launch_bounds__(kMvThreads) void mv_kernel(MvArgs a)
     f32x4 acc[COL ? NCH : 1];
 #pragma unroll
     for (int c = 0; c < (COL ? NCH : 1); ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int64_t r0 = (int64_t)g * a.rows_per;
-    const int64_t r1 = r0 + a.rows_per < a.M ? r0 + a.rows_per : a.M;
+    // Row blocks of RB rows are dealt to the work-groups in turn (block b to
+    // group b mod G), so the groups running at one time read neighbouring
+    // rows: the whole grid sweeps the matrix front to back, which keeps
+    // HBM closer to its streaming rate than one separate region per group.
+    const int64_t nblk = (a.M + RB - 1) / RB;
+    const int G = gridDim.x;
     int buf = 0;
-    for (int64_t i0 = r0; i0 < r1; i0 += RB) {
+    for (int64_t blk = g; blk < nblk; blk += G) {
+        const int64_t i0 = blk * RB;
+        const int64_t r0 = i0, r1 = i0 + RB < a.M ? i0 + RB : a.M;
         f32x4 x[RB][NCH];
         f32x4 y[DOTB ? RB : 1][NCH];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const int64_t row = i0 + r < r1 ? i0 + r : r0;  // rows past the group repeat r0
+            const int64_t row = i0 + r < r1 ? i0 + r : r0;  // rows past the matrix repeat r0
             const float *pa = a.A + row * a.N + c0;
             const float *pb = DOTB ? a.B + row * a.N + c0 : nullptr;
             const int64_t left = a.N - c0;  // columns of this slab inside the matrix
@@ -267,11 +273,10 @@ __global__ __launch_bounds__(256) void mv_finish_rows(MvArgs a, int slabs, int d
 
 struct MvPlan {
     int nch, rb, slabs, groups;
-    int64_t rows_per;
 };
 
-// Slab width 1024 * nch columns (nch a power of two up to max_nch); row
-// groups of at least 32 rows, at most 1024 work-groups in all.
+// Slab width 1024 * nch columns (nch a power of two up to max_nch); about
+// 512 work-groups in all, each taking at least 16 rows on average.
 MvPlan mv_plan(int64_t M, int64_t N, int max_nch, bool two_matrices)
 {
     MvPlan p;
@@ -284,14 +289,11 @@ MvPlan mv_plan(int64_t M, int64_t N, int max_nch, bool two_matrices)
     // (64 registers of row data per thread)
     p.rb = p.nch >= 16 ? 1 : 16 / p.nch;
     if (two_matrices && p.rb > 1) p.rb /= 2;
-    // row groups of at least 16 rows, about 512 work-groups in all
     int64_t groups = (M + 15) / 16;
     const int64_t cap = 512 / p.slabs > 1 ? 512 / p.slabs : 1;
     if (groups > cap) groups = cap;
     if (groups < 1) groups = 1;
-    p.rows_per = (M + groups - 1) / groups;
-    p.groups = (int)((M + p.rows_per - 1) / p.rows_per);
-    if (p.groups < 1) p.groups = 1;
+    p.groups = (int)groups;
     return p;
 }
 
@@ -303,7 +305,6 @@ size_t mv_plan_bytes(const MvPlan &p, int64_t M, int64_t N)
 template <int OPS>
 int launch_pass(const MvPlan &p, MvArgs a, hipStream_t s)
 {
-    a.rows_per = p.rows_per;
     const dim3 grid(p.groups, p.slabs);
 #define LI_MV(NCH, RB)                                                                          \
     if (p.nch == NCH && p.rb == RB) {                                                           \
