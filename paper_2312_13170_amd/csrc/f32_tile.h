@@ -1104,8 +1104,8 @@ struct F32Tile {
             }
     }
 
-    // The tile's current C values, read before the reduction starts so their
-    // latency hides behind it (out-of-range entries read C[0] and are unused).
+    // The tile's current C values, all loads issued before the first use
+    // (out-of-range entries read C[0] and are unused).
     __device__ __forceinline__ static void load_c(float (&cv)[TM][TN][16], const float *C,
                                                   int64_t ldc, int64_t M, int64_t N, int64_t m0,
                                                   int64_t n0)

@@ -30,7 +30,15 @@ __global__ __launch_bounds__(T::NT) void gemm_f32_kernel(const float *__restrict
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
     if (alpha != 0.f) T::mainloop(lds, A, lda, B, ldb, M, N, 0, K, m0, n0, acc);
-    T::epilogue_gemm(acc, C, ldc, M, N, m0, n0, alpha, beta);
+    if (beta != 0.f) {
+        // all of the tile's C loads issued together, then one wait (not a
+        // load-wait-store round trip per element)
+        float cv[T::TM][T::TN][16];
+        T::load_c(cv, C, ldc, M, N, m0, n0);
+        T::epilogue_gemm_loaded(acc, cv, C, ldc, M, N, m0, n0, alpha, beta);
+    } else {
+        T::epilogue_gemm(acc, C, ldc, M, N, m0, n0, alpha, 0.f);
+    }
 }
 
 template <class T>
