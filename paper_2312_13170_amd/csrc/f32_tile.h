@@ -1110,6 +1110,9 @@ struct F32Tile {
                                                   int64_t ldc, int64_t M, int64_t N, int64_t m0,
                                                   int64_t n0)
     {
+        // (not hoisted above the reduction, where the values would occupy
+        // registers through the main loop)
+        asm volatile("" ::: "memory");
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
@@ -1168,6 +1171,39 @@ struct F32Tile {
         const int lane = tid & 63, wave = tid >> 6;
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
         const bool diag_tile = m0 == n0;
+        if (mode == 2 && beta != 0.f) {
+            // four elements at a time: both triangles' current values loaded
+            // together, then the stores (not a load-wait-store round trip per
+            // element; four keep the registers of the kernels at their
+            // limit); each unordered pair (row, col) belongs to this element
+            // only
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int64_t col = n0 + acc_col(wn0, j, lane);
+#pragma unroll
+                    for (int v0 = 0; v0 < 16; v0 += 4) {
+                        float pv[4], qv[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int64_t row = m0 + acc_row(wm0, i, v0 + e, lane);
+                            const bool ok = row < M && col < M && !(diag_tile && row > col);
+                            pv[e] = S[ok ? row * M + col : 0];
+                            qv[e] = S[ok ? col * M + row : 0];
+                        }
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int64_t row = m0 + acc_row(wm0, i, v0 + e, lane);
+                            if (row >= M || col >= M || (diag_tile && row > col)) continue;
+                            const float val = acc[i][j][v0 + e];
+                            S[row * M + col] = combine(scale, val, beta, pv[e]);
+                            if (row != col) S[col * M + row] = combine(scale, val, beta, qv[e]);
+                        }
+                    }
+                }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
