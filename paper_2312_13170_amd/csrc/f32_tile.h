@@ -1171,6 +1171,53 @@ struct F32Tile {
         const int lane = tid & 63, wave = tid >> 6;
         const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
         const bool diag_tile = m0 == n0;
+        if (!diag_tile && (M & 3) == 0 && ((uintptr_t)S & 15) == 0) {
+            // Off-diagonal tile, order a multiple of 4, S 16-byte aligned:
+            // the four consecutive
+            // rows a lane holds for v = 4q .. 4q + 3 are four consecutive
+            // floats of the mirrored tile, so the lower-triangle copy goes
+            // out as one 16-byte store per lane (the direct copy is already
+            // coalesced across the lanes).  Rows come in aligned fours, so a
+            // four is either inside the matrix or wholly outside.
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int64_t col = n0 + acc_col(wn0, j, lane);
+                    if (col >= M) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t row = m0 + acc_row(wm0, i, 4 * q, lane);
+                        if (row >= M) continue;
+                        f32x4 val, old;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) val[e] = acc[i][j][4 * q + e];
+                        float *mir = S + col * M + row;
+                        if (mode == 2 && beta != 0.f) {
+                            float dir[4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) dir[e] = S[(row + e) * M + col];
+                            old = *reinterpret_cast<const f32x4 *>(mir);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                S[(row + e) * M + col] = combine(scale, val[e], beta, dir[e]);
+                                old[e] = combine(scale, val[e], beta, old[e]);
+                            }
+                            *reinterpret_cast<f32x4 *>(mir) = old;
+                        } else {
+                            // mode 0 and 2 (beta 0) scale; mode 1 is unscaled
+                            // off the diagonal
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                if (mode != 1) val[e] *= scale;
+                                S[(row + e) * M + col] = val[e];
+                            }
+                            *reinterpret_cast<f32x4 *>(mir) = val;
+                        }
+                    }
+                }
+            return;
+        }
         if (mode == 2 && beta != 0.f) {
             // four elements at a time: both triangles' current values loaded
             // together, then the stores (not a load-wait-store round trip per
