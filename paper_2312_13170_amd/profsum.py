@@ -82,6 +82,17 @@ def trace(args):
     for n, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         lines.append("| `%s` | %d | %.2f | %.2f | %.2f | %.1f%% |" % (
             short(n), len(v), sum(v) / len(v), min(v), max(v), 100.0 * sum(v) / total))
+    if args.timed_kernel:
+        # the launches after the warm-up ones: those of the timed loop (and
+        # whatever the program runs after it), to compare with its clock
+        for n, v in agg.items():
+            if args.timed_kernel in n and len(v) > args.skip:
+                t = v[args.skip:]
+                lines += ["", "Launches %d onwards of `%s` (after the %d warm-up launches, whose "
+                          "clocks are still rising): %d launches, mean %.2f us, median %.2f us." % (
+                              args.skip + 1, short(n)[:80], args.skip, len(t), sum(t) / len(t),
+                              sorted(t)[len(t) // 2])]
+                lines.append("timed_mean_us: %.3f" % (sum(t) / len(t)))
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
@@ -157,6 +168,9 @@ def main():
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("out")
+    t.add_argument("--timed-kernel", default=None,
+                   help="also report this kernel's mean over the launches after --skip")
+    t.add_argument("--skip", type=int, default=0, help="warm-up launches of --timed-kernel")
     h = sub.add_parser("hbm")
     h.add_argument("fetch_db")
     h.add_argument("write_db")
