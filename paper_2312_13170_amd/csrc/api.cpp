@@ -230,10 +230,9 @@ li_status li_mm3(int64_t NI, int64_t NJ, int64_t NK, int64_t NL, int64_t NM, con
         !li::matrix_bytes(NI, NJ, 4, &eb) || !li::matrix_bytes(NJ, NL, 4, &fb) ||
         !li::matrix_bytes(NI, NL, 4, &gb))
         return li::fail(LI_ERR_INVALID_SIZE, "matrix extent too large");
-    // E = A B reads A, B if it has output and a reduction; likewise F = C D;
-    // G = E F reads E and F if it has output and NJ > 0.
+    // E = A B reads A, B if it has output and a reduction; likewise F = C D.
+    // (E and F are outputs of the chain and checked as such below.)
     const bool e_reads = NI > 0 && NJ > 0 && NK > 0, f_reads = NJ > 0 && NL > 0 && NM > 0;
-    const bool g_reads = NI > 0 && NL > 0 && NJ > 0;
     const uint64_t ab_r = e_reads ? ab : 0, bb_r = e_reads ? bb : 0;
     const uint64_t cb_r = f_reads ? cb : 0, db_r = f_reads ? db : 0;
     if ((s = li::check_ptr("A", A, ab_r)) || (s = li::check_ptr("B", B, bb_r)) ||
