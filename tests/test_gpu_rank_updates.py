@@ -39,10 +39,12 @@ def ref_update(orc, A, B, C0, alpha, beta, two, rows=None):
 
 
 @pytest.mark.parametrize("two", [False, True], ids=["syrk", "syr2k"])
-@pytest.mark.parametrize("shape", [(130, 70), (257, 300), (64, 33), (300, 516)])
+@pytest.mark.parametrize("shape", [(130, 70), (257, 300), (64, 33), (300, 516), (300, 512)])
 def test_every_candidate(li, orc, two, shape):
     # ragged tiles in N and K; K = 300 and 516 take the vector and
-    # direct-to-LDS loads, K = 33 and 70 the scalar loads
+    # direct-to-LDS loads, K = 33 and 70 the scalar loads; K = 512 is whole
+    # K-tiles (direct-to-LDS loop with precomputed sources and clamped edge
+    # rows) and N = 300 a multiple of 4 (16-byte mirrored stores)
     N, K = shape
     A = synth.uniform_pm1(90, "A", (N, K))
     B = synth.uniform_pm1(90, "B", (N, K))
