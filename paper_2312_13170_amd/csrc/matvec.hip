@@ -246,8 +246,18 @@ __global__ __launch_bounds__(64 * kFinWaves) void mv_finish_cols(const float *__
     const int per = (groups + kFinWaves - 1) / kFinWaves;
     const int g0 = wave * per, g1 = g0 + per < groups ? g0 + per : groups;
     float s = 0.f;
-    if (j < N)
-        for (int g = g0; g < g1; ++g) s += part[(int64_t)g * N + j];
+    if (j < N) {
+        // eight loads in flight, then the additions in group order
+        int g = g0;
+        for (; g + 8 <= g1; g += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(g + u) * N + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; g < g1; ++g) s += part[(int64_t)g * N + j];
+    }
     sums[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && j < N) {
