@@ -286,7 +286,10 @@ typedef struct li_tile_config {
                                so both operands take 16-byte LDS reads;
                                8: direct HBM-to-LDS loads into a two-stage
                                ring (mode 2 when K is not a multiple of
-                               the K-tile) */
+                               the K-tile).  LI_KERNEL_GEMM_LP: the LDS
+                               layout instead (1: XOR-swizzled rows, 2:
+                               padded rows, 3: layout 1 filled by direct
+                               HBM-to-LDS loads) */
 } li_tile_config;
 
 int32_t li_tune_num_candidates(int32_t kernel);
