@@ -152,7 +152,7 @@ def main():
         return
 
     # ---------------------------------------------------------------- headline: 2mm 2048^4
-    c = synth.config(1)
+    c = synth.workload("mm2_2048")
     NI, NJ, NK, NL = c["NI"], c["NJ"], c["NK"], c["NL"]
     dA, dB, dC = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
     dD0 = torch.from_numpy(c["D"]).cuda()
@@ -286,7 +286,7 @@ def measure_rows(args, torch, li, synth, timer):
     reps = 30
 
     if "gemm256" in want:
-        c = synth.config(0)
+        c = synth.workload("gemm_256")
         A, B, C0 = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
         C = C0.clone()
         ms = timer.time(lambda: li.li_gemm(256, 256, 256, 1.5, A, B, 1.2, C), reps, 1)
@@ -295,7 +295,7 @@ def measure_rows(args, torch, li, synth, timer):
         del A, B, C0, C
 
     if "cov" in want or "corr" in want:
-        s = synth.config(2)
+        s = synth.workload("stats_4096x2048")
         X = torch.from_numpy(s["data"]).cuda()
         N, M = s["N"], s["M"]
         Y = torch.empty_like(X)
@@ -330,7 +330,7 @@ def measure_rows(args, torch, li, synth, timer):
         del X, Y, out, ws
 
     if "precision" in want:
-        p = synth.config(3)
+        p = synth.workload("precision_8192")
         M = N = K = 8192
         A, B = torch.from_numpy(p["A"]).cuda(), torch.from_numpy(p["B"]).cuda()
         C = torch.empty((M, N), device="cuda")
@@ -486,7 +486,7 @@ def measure_matvec(torch, li, synth, timer):
 
 
 def measure_grouped(torch, li, synth, timer):
-    b = synth.config(4)
+    b = synth.workload("batch_512_512")
     keep = []
     probs = []
     for d in b.gemm:

@@ -218,18 +218,21 @@ def batch_inputs(seed: int, n_gemm: int = 512, n_cov: int = 512, with_data: bool
     return b
 
 
-def config(i: int, seed: int | None = None, **kw):
-    """Inputs of synthetic configuration i (0..4)."""
-    s = i + 1 if seed is None else seed
-    if i == 0:
-        return gemm_inputs(256, 256, 256, s)
-    if i == 1:
-        return mm2_inputs(2048, 2048, 2048, 2048, s)
-    if i == 2:
-        return stats_inputs(4096, 2048, s)
-    if i == 3:
-        return precision_inputs(8192, 8192, 8192, s)
-    if i == 4:
-        return batch_inputs(s, **kw)
-    raise ValueError("configuration index must be 0..4")
+_WORKLOADS = {
+    # name: (default seed, builder)
+    "gemm_256": (1, lambda s, **kw: gemm_inputs(256, 256, 256, s)),
+    "mm2_2048": (2, lambda s, **kw: mm2_inputs(2048, 2048, 2048, 2048, s)),
+    "stats_4096x2048": (3, lambda s, **kw: stats_inputs(4096, 2048, s)),
+    "precision_8192": (4, lambda s, **kw: precision_inputs(8192, 8192, 8192, s)),
+    "batch_512_512": (5, lambda s, **kw: batch_inputs(s, **kw)),
+}
 
+
+def workload(name: str, seed: int | None = None, **kw):
+    """Inputs of a named workload: GEMM 256^3, 2mm 2048^4, statistics over
+    4096 samples x 2048 columns, the 8192^3 precision study, or the batch of
+    512 GEMM + 512 covariance instances.  Each has its own default seed."""
+    if name not in _WORKLOADS:
+        raise ValueError("unknown workload %r (known: %s)" % (name, ", ".join(_WORKLOADS)))
+    s0, build = _WORKLOADS[name]
+    return build(s0 if seed is None else seed, **kw)

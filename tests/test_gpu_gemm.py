@@ -83,9 +83,9 @@ def test_brute_force_small_shapes(li, orc):
                 assert normwise(out, ref) < 1e-6, (M, N, K)
 
 
-def test_config0(li, orc):
+def test_gemm_256_scaled(li, orc):
     say("gemm 256^3 alpha 1.5 beta 1.2")
-    c = synth.config(0)
+    c = synth.workload("gemm_256")
     out = run_gemm(li, c["A"], c["B"], c["C"], c["alpha"], c["beta"])
     ref = orc.gemm(c["A"], c["B"], c["C"], alpha=c["alpha"], beta=c["beta"])
     assert normwise(out, ref) < TOL_FP32
@@ -200,9 +200,9 @@ def test_mm2_identity(li, orc):
     assert np.all(np.abs(D - ref) <= bound * 1.0001 + 1e-45)
 
 
-def test_mm2_config1_sampled_rows(li, orc):
+def test_mm2_2048_sampled_rows(li, orc):
     say("mm2 2048^4 (sampled rows)")
-    c = synth.config(1)
+    c = synth.workload("mm2_2048")
     tmp, D = run_mm2(li, c)
     rows = np.array([0, 1, 127, 128, 1023, 1500, 2046, 2047])
     rt, rD = orc.mm2(c["A"], c["B"], c["C"], c["D"], alpha=c["alpha"], beta=c["beta"], rows=rows)

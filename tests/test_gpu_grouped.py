@@ -110,9 +110,9 @@ def test_small_batch_all_instances(li, orc):
     plan.close()
 
 
-def test_config4_batch(li, orc):
+def test_grouped_1024_instances(li, orc):
     say("grouped 512 GEMM + 512 covariance instances")
-    b = synth.config(4)
+    b = synth.workload("batch_512_512")
     batch = Batch(li, b)
     plan = li.li_group_plan_create(batch.problems)
     assert plan.flops > 1e10

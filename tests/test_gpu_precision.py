@@ -126,9 +126,9 @@ def test_every_tile_shape(li, orc):
         li.li_tune_force(li.LI_KERNEL_GEMM_LP, -1)
 
 
-def test_config3_sampled_rows(li, orc):
+def test_precision_8192_sampled_rows(li, orc):
     say("precision 8192^3 (sampled rows)")
-    c = synth.config(3)
+    c = synth.workload("precision_8192")
     A, B = c["A"], c["B"]
     rows = np.array([0, 1, 255, 256, 4095, 5000, 8190, 8191])
     exact = orc.gemm_quantised(A, B, "exact", rows=rows)

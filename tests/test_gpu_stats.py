@@ -111,9 +111,9 @@ def test_every_tile_shape(li, orc):
         li.li_tune_force(li.LI_KERNEL_SYRK_F32, -1)
 
 
-def test_config2_full_size_sampled(li, orc):
+def test_stats_4096x2048_sampled(li, orc):
     say("stats 4096 x 2048 (sampled entries)")
-    inp = synth.config(2)
+    inp = synth.workload("stats_4096x2048")
     X = inp["data"]
     N, M = X.shape
     pa = synth.integer_matrix(44, "pa", (200,), 0, M - 1).astype(np.int64)
@@ -214,9 +214,9 @@ def test_fused_constant_columns(li):
         assert np.all(np.delete(corr[j, :], j) == 0.0)
 
 
-def test_fused_config2(li, orc):
+def test_fused_4096x2048(li, orc):
     say("fused stats 4096 x 2048")
-    X = synth.config(2)["data"]
+    X = synth.workload("stats_4096x2048")["data"]
     N, M = X.shape
     pa = synth.integer_matrix(48, "pa", (100,), 0, M - 1).astype(np.int64)
     pb = synth.integer_matrix(48, "pb", (100,), 0, M - 1).astype(np.int64)

@@ -4,6 +4,7 @@ import math
 import os
 
 import numpy as np
+import pytest
 
 from paper_2312_13170_amd import synth
 
@@ -57,9 +58,11 @@ def test_normal_moments():
     assert abs(z.mean()) < 0.01 and abs(z.std() - 1.0) < 0.01
 
 
-def test_config_shapes():
-    c0 = synth.config(0)
+def test_workload_shapes():
+    c0 = synth.workload("gemm_256")
     assert c0["A"].shape == (256, 256) and c0["alpha"] == 1.5 and c0["beta"] == 1.2
+    with pytest.raises(ValueError):
+        synth.workload("gemm_255")
     s = synth.stats_inputs(256, 64, seed=3)
     assert s["data"].shape == (256, 64)
     assert np.all((s["mu"] >= -10) & (s["mu"] < 10))
