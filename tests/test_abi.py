@@ -260,3 +260,16 @@ def test_fused_statistics_argument_rules(li):
     assert lib.li_covariance_fused(M, N, FAKE, FAKE + 8, FAKE + 2 * xb, FAKE + 4 * xb, ws, None) == li.LI_ERR_OVERLAP
     assert lib.li_correlation_fused(M, N, 0.1, FAKE, FAKE + xb, None, FAKE + 2 * xb, FAKE + 4 * xb, ws,
                                     None) == li.LI_ERR_NULL_POINTER
+
+
+def test_binding_refuses_to_load_without_library(tmp_path):
+    # A copy of the binding in a folder with no libli.so must raise on
+    # import: the package has no path that computes without the library.
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2312_13170_amd", "li.py")
+    dst = tmp_path / "li.py"
+    dst.write_text(open(src).read())
+    spec = importlib.util.spec_from_file_location("li_without_library", str(dst))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="no fallback"):
+        spec.loader.exec_module(mod)
