@@ -286,7 +286,8 @@ struct MvPlan {
 };
 
 // Slab width 1024 * nch columns (nch a power of two up to max_nch); about
-// 512 work-groups in all, each taking at least 16 rows on average.
+// 512 work-groups in all (256 for rows of 8192 columns or more), each taking
+// at least 16 rows on average.
 MvPlan mv_plan(int64_t M, int64_t N, int max_nch, bool two_matrices)
 {
     MvPlan p;
@@ -299,13 +300,19 @@ MvPlan mv_plan(int64_t M, int64_t N, int max_nch, bool two_matrices)
     // (64 registers of row data per thread)
     p.rb = p.nch >= 16 ? 1 : 16 / p.nch;
     // Two matrices: half as many rows per step, except on grids of several
-    // slabs (N above 8192), where the slabs share the 512 work-groups, each
+    // slabs (N above 8192), where the slabs share the work-groups, each
     // group takes more rows, and one row per step leaves its reduction and
     // barrier exposed (measured at 16384 columns: two rows 4% faster; with
     // one slab, two rows were 5-7% slower).
     if (two_matrices && p.rb > 1 && p.slabs == 1) p.rb /= 2;
+    // Wide rows: every work-group writes a row of N column partials that the
+    // finish kernel reads back, and with N >= 8192 half the groups was faster
+    // (bicg / atax 8192^2 4-6%, atax 16384^2 9%, bicg / mvt 16384^2 2-3%);
+    // narrow rows need the larger grid (bicg 32768 x 2048: 256 groups 40%
+    // slower).
+    const int64_t total = N >= 8192 ? 256 : 512;
     int64_t groups = (M + 15) / 16;
-    const int64_t cap = 512 / p.slabs > 1 ? 512 / p.slabs : 1;
+    const int64_t cap = total / p.slabs > 1 ? total / p.slabs : 1;
     if (groups > cap) groups = cap;
     if (groups < 1) groups = 1;
     p.groups = (int)groups;
