@@ -25,6 +25,11 @@
  *    unknown enum value return an error and launch nothing.  The
  *    no-overlap rule is the run-time form of the alias checks that the
  *    paper's transformations rely on (Sec. V-A, VI-A).
+ *  - Workspaces: caller-owned device memory of at least the size that the
+ *    matching *_workspace_bytes call returns, 16-byte aligned (a NULL,
+ *    short or misaligned workspace is LI_ERR_WORKSPACE); no initial contents
+ *    are needed and its contents after a call are unspecified.  Calls that
+ *    may run at the same time need separate workspaces.
  *  - Degenerate sizes: a zero output extent is a no-op; K == 0 gives
  *    C = beta*C; alpha == 0 means A and B are not read; beta == 0 means C
  *    is not read (NaN in C does not propagate).
@@ -154,9 +159,11 @@ li_status li_correlation(int64_t M, int64_t N, double eps, const float *data,
  * workspace as li_covariance / li_correlation, without data_out; mean and
  * stddev are bitwise the same.  Inside the contraction each element is
  * centred in FP32 with the mean rounded to FP32, which shifts a column's
- * centred values by the same amount; that changes the result by about
- * N d_a d_b (d <= 2^-24 |mean|), far below its FP32 rounding, so cov / corr
- * agree with the unfused results to a few units in the last place. */
+ * centred values by the same d (|d| <= 2^-24 |mean|); the known product
+ * term N d_a d_b (times the factors for correlation) is subtracted before
+ * the result is written, so cov / corr agree with the unfused results to
+ * a few units in the last place also for means far from zero relative to
+ * the spread. */
 li_status li_covariance_fused(int64_t M, int64_t N, const float *data, double *mean, float *cov,
                               void *workspace, size_t workspace_bytes, li_stream stream);
 li_status li_correlation_fused(int64_t M, int64_t N, double eps, const float *data,

@@ -134,9 +134,7 @@ li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *
     const bool lp = p != LI_FP32 && ab > 0;
     if (lp) {
         const size_t need = li::lp_workspace_bytes(M, N, K, (int)p);
-        if (workspace_bytes < need || (need > 0 && workspace == nullptr))
-            return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
-                            workspace_bytes);
+        if ((s = li::check_workspace(workspace, workspace_bytes, need))) return s;
         const Span ws{workspace, need};
         if ((s = li::check_no_overlap("workspace", ws, "A", Span{A, ab})) ||
             (s = li::check_no_overlap("workspace", ws, "B", Span{B, bb})) ||
@@ -297,8 +295,7 @@ li_status rank_update(int64_t N, int64_t K, float alpha, const float *A, const f
         (s = li::check_ptr("C", C, cb)))
         return s;
     const size_t need = reads ? li::sym_rows_split_bytes(N) : 0;
-    if (ws_bytes < need || (need > 0 && ws == nullptr))
-        return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if ((s = li::check_workspace(ws, ws_bytes, need))) return s;
     const Span sA{A, ab}, sB{B, bb}, sC{C, cb}, sW{ws, need};
     if ((s = li::check_no_overlap("C", sC, "A", sA)) || (s = li::check_no_overlap("C", sC, "B", sB)) ||
         (s = li::check_no_overlap("workspace", sW, "A", sA)) ||
@@ -332,12 +329,12 @@ size_t li_stats_workspace_bytes(int64_t M, int64_t N) { return li::stats_workspa
 
 }  // extern "C"
 
-namespace {
+namespace li {
 
 // fused: no data_out (the centring happens inside the contraction's loads)
-li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float *data,
-                       float *data_out, double *mean, double *stdv, float *out, void *ws,
-                       size_t ws_bytes, li_stream stream, bool fused = false)
+li_status stats_call(bool corr, int64_t M, int64_t N, double eps, const float *data,
+                     float *data_out, double *mean, double *stdv, float *out, void *ws,
+                     size_t ws_bytes, li_stream stream, bool fused, WorkspaceNeed need_kind)
 {
     li_status s;
     if ((s = li::check_nonneg("M", M)) || (s = li::check_nonneg("N", N))) return s;
@@ -357,9 +354,11 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
         (s = li::check_ptr(corr ? "corr" : "cov", out, sb)))
         return s;
     if (corr && (s = li::check_ptr("stddev", stdv, vb))) return s;
-    const size_t need = li::stats_workspace_bytes(M, N);
-    if (ws_bytes < need || (need > 0 && ws == nullptr))
-        return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    const int cfg = M > 0 ? li::tune_pick(LI_KERNEL_SYRK_F32, M, M, N) : 0;
+    const size_t need = need_kind == kNeedAnyCandidate ? li::stats_workspace_bytes(M, N)
+                        : M > 0 ? li::stats_part_bytes(M, N) + li::syrk_split_bytes_cfg(cfg, M)
+                                : 0;
+    if ((s = li::check_workspace(ws, ws_bytes, need))) return s;
     const Span sX{data, xb}, sY{data_out, yb}, sM{mean, vb}, sS{stdv, corr ? vb : 0}, sO{out, sb},
         sW{ws, need};
     if (!fused && data_out != data && (s = li::check_no_overlap("data_out", sY, "data", sX))) return s;
@@ -377,7 +376,6 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
                                        fused ? 0 : 1),
                       "column statistics launch")))
         return s;
-    const int cfg = li::tune_pick(LI_KERNEL_SYRK_F32, M, M, N);
     const float scale = corr ? 1.0f : (float)(1.0 / (double)(N - 1));
     float *split_ws = (float *)((char *)ws + li::stats_part_bytes(M, N));
     if (fused)
@@ -386,6 +384,18 @@ li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float 
                         "fused symmetric contraction launch");
     return launched(li::launch_syrk_f32(cfg, M, N, data_out, out, corr ? 1 : 0, scale, split_ws, stream),
                     "symmetric contraction launch");
+}
+
+}  // namespace li
+
+namespace {
+
+li_status stats_common(bool corr, int64_t M, int64_t N, double eps, const float *data,
+                       float *data_out, double *mean, double *stdv, float *out, void *ws,
+                       size_t ws_bytes, li_stream stream, bool fused = false)
+{
+    return li::stats_call(corr, M, N, eps, data, data_out, mean, stdv, out, ws, ws_bytes, stream,
+                          fused, li::kNeedAnyCandidate);
 }
 
 }  // namespace
@@ -456,8 +466,7 @@ li_status matvec_common(int op, int64_t M, int64_t N, const Vec *ins, int nin, c
         if ((s = li::check_ptr(outs[i].name, outs[i].p, b))) return s;
     }
     const size_t need = work ? li::matvec_workspace_bytes(M, N) : 0;
-    if (ws_bytes < need || (need > 0 && ws == nullptr))
-        return li::fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if ((s = li::check_workspace(ws, ws_bytes, need))) return s;
     const Span sW{ws, need};
     for (int o = 0; o < nout; ++o) {
         for (int i = 0; i < nin; ++i)

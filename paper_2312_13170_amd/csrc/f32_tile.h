@@ -316,8 +316,8 @@ struct F32Tile {
     // Centring with the rounded mean m = mean + d shifts every centred value
     // of a column by the same d (|d| <= 2^-24 |mean|); the products then gain
     // d_a sum_i y_ib + d_b sum_i y_ia + n d_a d_b, where the sums of centred
-    // values vanish, so the contraction changes by about n d_a d_b:
-    // far below FP32 rounding of the result.
+    // values vanish, so the contraction gains n d_a d_b, which the symmetric
+    // kernels subtract before their epilogue (fused_shift_correct).
     // With PF == 4 the transform is applied to the matrix-core operands
     // after the LDS reads instead (same FP32 operations): rma / rfa hold the
     // statistics of the A columns this lane reads (one per 32-column block

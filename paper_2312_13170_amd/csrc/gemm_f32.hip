@@ -96,6 +96,29 @@ size_t syrk_split_bytes(int64_t n)
     return best;
 }
 
+size_t syrk_split_bytes_cfg(int cfg, int64_t n)
+{
+    // what run_sym touches for this candidate: split partials of every
+    // upper tile, or two stream-K pieces per work-group of its grid
+    switch (cfg) {
+#define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                   \
+    case IDX: {                                                                                \
+        const int64_t t = (n + BM - 1) / BM;                                                   \
+        if (SK > 1) return (size_t)SK * (size_t)(t * (t + 1) / 2) * BM * BN * sizeof(float);   \
+        if (SK == 0) {                                                                         \
+            int g = device_cu_count() * (64 * WM * WN >= 1024 ? 1 : 2);                        \
+            if (g > kStreamMaxGroups) g = kStreamMaxGroups;                                    \
+            return (size_t)2 * g * BM * BN * sizeof(float);                                    \
+        }                                                                                      \
+        return 0;                                                                              \
+    }
+        LI_SYRK_F32_CANDIDATES(LI_CASE)
+#undef LI_CASE
+    default:
+        return syrk_split_bytes(n);
+    }
+}
+
 int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode, float scale,
                     float *split_ws, void *stream)
 {

@@ -29,6 +29,11 @@ bool overlaps(Span a, Span b);
 li_status check_nonneg(const char *what, int64_t v);
 li_status check_ptr(const char *what, const void *p, uint64_t bytes);
 li_status check_no_overlap(const char *out_name, Span out, const char *in_name, Span in);
+// Caller workspaces: at least `need` bytes, non-NULL when need > 0, and
+// aligned to kWorkspaceAlign bytes (kernels read and write them with 16-byte
+// vector accesses; sub-buffers inside start at multiples of 256 bytes).
+constexpr uintptr_t kWorkspaceAlign = 16;
+li_status check_workspace(const void *ws, size_t ws_bytes, size_t need);
 
 // ---------------------------------------------------------------- device
 li_status ensure_device();   // gfx950 check for the current device
@@ -58,6 +63,8 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
 // forced to 1.0 (correlation).  Candidates with split_k > 1 need split_ws of
 // syrk_split_bytes(M) bytes (the largest any candidate uses).
 size_t syrk_split_bytes(int64_t M);
+// the part of that one candidate uses (its grid on the current device)
+size_t syrk_split_bytes_cfg(int cfg, int64_t M);
 int launch_syrk_f32(int cfg, int64_t M, int64_t N, const float *Y, float *S, int mode,
                     float scale, float *split_ws, void *stream);
 
@@ -92,6 +99,17 @@ int launch_stats(int64_t M, int64_t N, const float *X, float *Y, double *mean, d
                  int correlation, double eps, void *ws, void *stream, int centre = 1);
 // the per-column normalisation factors inside the statistics workspace
 const double *stats_factor(const void *ws, int64_t M, int64_t N);
+
+// Covariance (corr false) or correlation through the statistics,
+// centring (unless fused) and contraction kernels, after the validation of
+// the li_covariance / li_correlation entry points.  The workspace must hold
+// what any contraction candidate may use (kNeedAnyCandidate, the size that
+// li_stats_workspace_bytes reports) or only what the candidate chosen for
+// this problem uses on the current device (kNeedChosenCandidate).
+enum WorkspaceNeed { kNeedAnyCandidate = 0, kNeedChosenCandidate = 1 };
+li_status stats_call(bool corr, int64_t M, int64_t N, double eps, const float *data,
+                     float *data_out, double *mean, double *stdv, float *out, void *ws,
+                     size_t ws_bytes, void *stream, bool fused, WorkspaceNeed need_kind);
 
 // Matrix-vector kernels (matvec.hip), A (and B) M x N, M, N >= 1:
 //   kMvAtax    v1 = x; o1 = tmp = A x; o2 = y = A^T tmp

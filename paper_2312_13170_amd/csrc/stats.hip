@@ -140,10 +140,13 @@ __global__ __launch_bounds__(256) void centre_kernel_v4(const float *X, float *Y
 
 // Layout: [chunk partials nsplit x 2 x M doubles][factor M doubles]
 //         [split-K partials of the contraction, syrk_split_bytes(M)]
+// The statistics part is rounded up to 256 bytes, so the contraction's
+// partials (16-byte vector accesses) start aligned for any M.
 size_t stats_part_bytes(int64_t M, int64_t N)
 {
     StatsPlan p = stats_plan(M, N);
-    return (size_t)(p.nsplit * 2 * M + M) * sizeof(double);
+    const size_t b = (size_t)(p.nsplit * 2 * M + M) * sizeof(double);
+    return (b + 255) / 256 * 256;
 }
 
 size_t stats_workspace_bytes(int64_t M, int64_t N)

@@ -55,6 +55,49 @@ __device__ __forceinline__ void sym_reduce(float *lds, const SymArgs &a, int64_t
     if (FORM == kSymRows2) T::mainloop(lds, a.Z, a.ld, a.X, a.ld, a.n, a.n, kbeg, kend, m0, n0, acc);
 }
 
+// Fused centring (T::XFORM) subtracts the column mean rounded to FP32,
+// m = mean + d, so every centred value of a column is off by the same -d
+// (times the FP32 factor f for correlation).  The values centred with the
+// FP64 mean sum to zero over a column (up to that mean's rounding), so the
+// reduced products over the N samples gain N f_a f_b d_a d_b, which is
+// removed here before the epilogue: each value is again the contraction of
+// the FP64-centred data, up to the FP32 rounding of its products and sums.  The term is relative to the
+// result about 2^-48 (|mean_a| / sd_a)(|mean_b| / sd_b): negligible for
+// means within a few thousand standard deviations, larger than the FP32
+// tolerance beyond about 1e5.
+template <class T>
+__device__ __forceinline__ void fused_shift_correct(f32x16 (&acc)[T::TM][T::TN], const SymArgs &a,
+                                                    int64_t m0, int64_t n0, int vtid = -1)
+{
+    if constexpr (T::XFORM != 0) {
+        const int tid = vtid >= 0 ? vtid : (int)threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm0 = (wave / T::WN) * (T::BM / T::WM), wn0 = (wave % T::WN) * (T::BN / T::WN);
+        const double rn = sqrt((double)a.kdim);
+        // sqrt(N) f d of column c (0 outside the matrix, whose values are
+        // never stored)
+        auto shift = [&](int64_t c) -> double {
+            if (c >= a.n) return 0.0;
+            const double mu = a.mean[c];
+            const double d = (double)(float)mu - mu;
+            const double f = T::XFORM == 2 ? (double)(float)a.factor[c] : 1.0;
+            return rn * f * d;
+        };
+        double cb[T::TN];
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) cb[j] = shift(n0 + T::acc_col(wn0, j, lane));
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const double ca = shift(m0 + T::acc_row(wm0, i, v, lane));
+#pragma unroll
+                for (int j = 0; j < T::TN; ++j)
+                    acc[i][j][v] = (float)((double)acc[i][j][v] - ca * cb[j]);
+            }
+    }
+}
+
 // Raw accumulators of one tile as a partial result: BM * BN floats, laid out
 // chunk-major ([chunk][thread] float4s, chunk = 4 consecutive registers), so
 // one store or load instruction of a wave touches 1 KiB contiguously.
@@ -100,7 +143,10 @@ __global__ __launch_bounds__(T::NT) void sym_kernel(SymArgs a, int tiles)
     const int64_t m0 = (int64_t)tm * T::BM, n0 = (int64_t)tn * T::BN;
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
-    if (a.reads) sym_reduce<T, FORM>(lds, a, 0, a.kdim, m0, n0, acc);
+    if (a.reads) {
+        sym_reduce<T, FORM>(lds, a, 0, a.kdim, m0, n0, acc);
+        fused_shift_correct<T>(acc, a, m0, n0);
+    }
     T::epilogue_syrk(acc, a.S, a.n, m0, n0, a.mode, a.scale, a.beta);
 }
 
@@ -149,6 +195,7 @@ __global__ __launch_bounds__(kReduceThreads) void sym_split_reduce_kernel(SymArg
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
     for (int s = 0; s < splits; ++s) add_partial<T>(acc, part + (int64_t)(s * nb + t) * T::BM * T::BN, vtid);
+    fused_shift_correct<T>(acc, a, (int64_t)tm * T::BM, (int64_t)tn * T::BN, vtid);
     T::epilogue_syrk(acc, a.S, a.n, (int64_t)tm * T::BM, (int64_t)tn * T::BN, a.mode, a.scale, a.beta,
                      vtid);
 }
@@ -197,9 +244,10 @@ __global__ __launch_bounds__(T::NT) void sym_streamk_kernel(SymArgs a, float *__
         f32x16 acc[T::TM][T::TN];
         T::zero(acc);
         sym_reduce<T, FORM>(lds, a, k0 * T::BK, kend, m0, n0, acc);
-        if (k0 == 0 && k1 == kt)
+        if (k0 == 0 && k1 == kt) {
+            fused_shift_correct<T>(acc, a, m0, n0);
             T::epilogue_syrk(acc, a.S, a.n, m0, n0, a.mode, a.scale, a.beta);
-        else
+        } else
             store_partial<T>(acc, part + ((int64_t)g * 2 + (it == beg ? 0 : 1)) * T::BM * T::BN,
                              threadIdx.x);
         it = stop;
@@ -227,6 +275,7 @@ __global__ __launch_bounds__(kReduceThreads) void sym_streamk_fixup_kernel(SymAr
         const int slot = sk_begin(g, total, G) / kt == t ? 0 : 1;
         add_partial<T>(acc, part + ((int64_t)g * 2 + slot) * T::BM * T::BN, vtid);
     }
+    fused_shift_correct<T>(acc, a, (int64_t)tm * T::BM, (int64_t)tn * T::BN, vtid);
     T::epilogue_syrk(acc, a.S, a.n, (int64_t)tm * T::BM, (int64_t)tn * T::BN, a.mode, a.scale, a.beta,
                      vtid);
 }

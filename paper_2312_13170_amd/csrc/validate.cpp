@@ -55,6 +55,17 @@ li_status check_ptr(const char *what, const void *p, uint64_t bytes)
     return LI_OK;
 }
 
+li_status check_workspace(const void *ws, size_t ws_bytes, size_t need)
+{
+    if (need == 0) return LI_OK;
+    if (ws == nullptr || ws_bytes < need)
+        return fail(LI_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                    ws == nullptr ? (size_t)0 : ws_bytes);
+    if (((uintptr_t)ws & (kWorkspaceAlign - 1)) != 0)
+        return fail(LI_ERR_WORKSPACE, "workspace must be %d-byte aligned", (int)kWorkspaceAlign);
+    return LI_OK;
+}
+
 li_status check_no_overlap(const char *out_name, Span out, const char *in_name, Span in)
 {
     if (overlaps(out, in))

@@ -105,7 +105,7 @@ def test_rank_update_argument_rules(li):
     assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + 4, W, ws, None) == li.LI_ERR_OVERLAP
     # workspace too small, and overlapping C
     assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + ab, W, ws - 4, None) == li.LI_ERR_WORKSPACE
-    assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + ab, FAKE + ab + 8, ws, None) == li.LI_ERR_OVERLAP
+    assert lib.li_syrk(N, K, 1.0, FAKE, 0.0, FAKE + ab, FAKE + ab + 16, ws, None) == li.LI_ERR_OVERLAP
     # syr2k: B NULL, C overlapping B
     assert lib.li_syr2k(N, K, 1.0, FAKE, None, 0.0, FAKE + 2 * ab, W, ws, None) == li.LI_ERR_NULL_POINTER
     assert lib.li_syr2k(N, K, 1.0, FAKE, FAKE + ab, 0.0, FAKE + ab + 4, W, ws, None) == li.LI_ERR_OVERLAP
@@ -238,7 +238,7 @@ def test_matvec_argument_rules(li):
     assert lib.li_atax(M, N, None, x, t, y, W, ws, None) == li.LI_ERR_NULL_POINTER
     assert lib.li_atax(M, N, FAKE, x, x + 4, y, W, ws, None) == li.LI_ERR_OVERLAP
     assert lib.li_atax(M, N, FAKE, x, t, y, W, ws - 4, None) == li.LI_ERR_WORKSPACE
-    assert lib.li_atax(M, N, FAKE, x, t, y, FAKE + 8, ws, None) == li.LI_ERR_OVERLAP
+    assert lib.li_atax(M, N, FAKE, x, t, y, FAKE + 16, ws, None) == li.LI_ERR_OVERLAP
     # mvt: x1 overlapping x2 (both in/out)
     assert lib.li_mvt(M, N, FAKE, x, x + 1024, t, t + 16, W, ws, None) == li.LI_ERR_OVERLAP
     # gesummv: B NULL, y overlapping B
@@ -273,3 +273,25 @@ def test_binding_refuses_to_load_without_library(tmp_path):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError, match="no fallback"):
         spec.loader.exec_module(mod)
+
+
+def test_misaligned_workspace_rejected(li):
+    # every workspace must be 16-byte aligned (the kernels access it with
+    # 16-byte vectors); an address 8 bytes off is refused before any launch
+    lib = li._lib
+    M, N = 9, 16
+    xb = 4 * M * N
+    W = FAKE + (1 << 24)
+    ws = lib.li_stats_workspace_bytes(M, N)
+    assert lib.li_covariance(M, N, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 3 * xb, W + 8, ws, None) == li.LI_ERR_WORKSPACE
+    assert "aligned" in li.li_last_error()
+    assert lib.li_covariance_fused(M, N, FAKE, FAKE + 2 * xb, FAKE + 3 * xb, W + 8, ws, None) == li.LI_ERR_WORKSPACE
+    n, k = 16, 8
+    ab = 4 * n * k
+    ws = lib.li_syrk_workspace_bytes(n, k)
+    assert lib.li_syrk(n, k, 1.0, FAKE, 0.0, FAKE + ab, W + 4, ws, None) == li.LI_ERR_WORKSPACE
+    need = lib.li_gemm_ex_workspace_bytes(8, 8, 8, li.LI_BF16)
+    assert lib.li_gemm_ex(8, 8, 8, 1.0, FAKE, FAKE + 4096, 0.0, FAKE + 8192, li.LI_BF16, W + 8, need, None) == li.LI_ERR_WORKSPACE
+    ws = lib.li_matvec_workspace_bytes(32, 32)
+    assert lib.li_bicg(32, 32, FAKE, FAKE + 8192, FAKE + 8320, FAKE + 8448, FAKE + 8576, W + 12, ws, None) == li.LI_ERR_WORKSPACE
+

@@ -96,8 +96,12 @@ def test_against_oracle(li, orc, N, M, inplace):
     assert np.array_equal(corr, corr.T) and np.all(np.diag(corr) == 1.0)
 
 
-def test_every_tile_shape(li, orc):
-    N, M = 333, 300
+# M = 301: an odd order, so the FP64 statistics part of the workspace is not
+# a multiple of 16 bytes before rounding; the split and stream-K candidates
+# put their 16-byte partials after it
+@pytest.mark.parametrize("M", [300, 301])
+def test_every_tile_shape(li, orc, M):
+    N = 333
     X = synth.stats_inputs(N, M, seed=43)["data"]
     _, _, rcov = orc.covariance(X, want_y=False)
     try:
@@ -111,30 +115,32 @@ def test_every_tile_shape(li, orc):
         li.li_tune_force(li.LI_KERNEL_SYRK_F32, -1)
 
 
-def test_stats_4096x2048_sampled(li, orc):
-    say("stats 4096 x 2048 (sampled entries)")
-    inp = synth.workload("stats_4096x2048")
-    X = inp["data"]
-    N, M = X.shape
-    pa = synth.integer_matrix(44, "pa", (200,), 0, M - 1).astype(np.int64)
-    pb = synth.integer_matrix(44, "pb", (200,), 0, M - 1).astype(np.int64)
-    pa = np.concatenate([pa, [0, M - 1, 5]])
-    pb = np.concatenate([pb, [M - 1, M - 1, 5]])
+@pytest.fixture(scope="module")
+def stats4096(orc):
+    """The 4096 x 2048 statistics workload and its full FP64 oracle results."""
+    say("stats 4096 x 2048: oracle covariance and correlation (every entry)")
+    X = synth.workload("stats_4096x2048")["data"]
+    rY, rmean, rcov = orc.covariance(X)
+    rYc, _, rstd, rcorr = orc.correlation(X)
+    return dict(X=X, rY=rY, rmean=rmean, rcov=rcov, rYc=rYc, rstd=rstd, rcorr=rcorr)
+
+
+def test_stats_4096x2048_full(li, stats4096):
+    # every entry of the centred data, the statistics and cov / corr
+    X = stats4096["X"]
     for corr in (False, True):
+        say("stats 4096 x 2048", "correlation" if corr else "covariance")
         Y, mean, std, out = run_stats(li, X, corr=corr)
-        rY, rmean, rstd = orc.centred_data(X, correlation=corr)
-        assert np.allclose(mean, rmean, rtol=1e-12, atol=1e-12)
-        assert normwise(Y, rY) < 1e-7
+        assert np.allclose(mean, stats4096["rmean"], rtol=1e-12, atol=1e-12)
+        assert normwise(Y, stats4096["rYc" if corr else "rY"]) < 1e-7
         if corr:
-            assert np.allclose(std, rstd, rtol=1e-12)
-            ref = orc.correlation_entries(X, pa, pb)
-        else:
-            ref = orc.covariance_entries(X, pa, pb)
-        got = out[pa, pb]
-        # entry error against the largest magnitude of the result (normwise)
-        scale = np.max(np.abs(np.diag(out))) if not corr else 1.0
-        assert np.max(np.abs(got - ref)) / scale < TOL_FP32
+            assert np.allclose(std, stats4096["rstd"], rtol=1e-12)
+        err = normwise(out, stats4096["rcorr" if corr else "rcov"])
+        say("   normwise error %.3e" % err)
+        assert err < TOL_FP32
         assert np.array_equal(out, out.T)
+        if corr:
+            assert np.all(np.diag(out) == 1.0)
 
 
 # ------------------------------------------------ centring fused into the contraction
@@ -153,9 +159,9 @@ def run_fused(li, X, corr, eps=0.1):
     return host(mean), (host(std) if corr else None), host(out)
 
 
-# the fused loads centre in FP32 with the mean split into two floats: each
-# centred value is within about one rounding of the FP64 centring, so the
-# contraction agrees with the two-kernel path to a few ulp
+# the fused loads centre in FP32 with the mean rounded to FP32 and the
+# kernel removes the known shift this causes, so the contraction agrees with
+# the two-kernel path to a few ulp
 FUSED_VS_UNFUSED = 2e-6
 
 
@@ -214,17 +220,49 @@ def test_fused_constant_columns(li):
         assert np.all(np.delete(corr[j, :], j) == 0.0)
 
 
-def test_fused_4096x2048(li, orc):
-    say("fused stats 4096 x 2048")
-    X = synth.workload("stats_4096x2048")["data"]
-    N, M = X.shape
-    pa = synth.integer_matrix(48, "pa", (100,), 0, M - 1).astype(np.int64)
-    pb = synth.integer_matrix(48, "pb", (100,), 0, M - 1).astype(np.int64)
+def test_fused_4096x2048(li, stats4096):
+    say("fused stats 4096 x 2048 (every entry)")
+    X = stats4096["X"]
     for corr in (False, True):
         _, mean, std, out = run_stats(li, X, corr=corr)
         fmean, fstd, fout = run_fused(li, X, corr=corr)
         assert np.array_equal(mean, fmean)
         assert normwise(fout, out) < FUSED_VS_UNFUSED
-        ref = orc.correlation_entries(X, pa, pb) if corr else orc.covariance_entries(X, pa, pb)
-        scale = 1.0 if corr else np.max(np.abs(np.diag(fout)))
-        assert np.max(np.abs(fout[pa, pb] - ref)) / scale < TOL_FP32
+        err = normwise(fout, stats4096["rcorr" if corr else "rcov"])
+        say("   %s normwise error %.3e" % ("correlation" if corr else "covariance", err))
+        assert err < TOL_FP32
+
+
+@pytest.mark.parametrize("ratio", [1e5, 1e6])
+@pytest.mark.parametrize("N", [512, 333])
+def test_fused_means_far_from_zero(li, orc, ratio, N):
+    # columns whose mean is 1e5 or 1e6 standard deviations from zero: the
+    # FP32-rounded mean used by the fused loads is off by up to 2^-24 |mean|,
+    # i.e. up to 0.06 standard deviations, and the kernel must remove the
+    # N d_a d_b this adds to every product (without that step the fused
+    # result is off by ~1e-3 at 1e6).  Both paths are held to the oracle
+    # bound.  They are not compared with each other here: the centred values
+    # of such data carry only 16-19 significant bits, and the FP32 sums of
+    # their squares round differently in the two paths (the unfused diagonal
+    # is 2-7e-6 off at N = 512, as a round-to-nearest emulation of the same
+    # FP32 sums predicts, while x - fl32(mean) is exact with a few bits and
+    # its sums are exact).
+    M = 260
+    say("fused stats, |mean| / sd =", ratio, "N =", N)
+    base = synth.stats_inputs(N, M, seed=49)["data"].astype(np.float64)
+    mu = np.mean(base, axis=0)
+    sd = np.std(base, axis=0)
+    z = (base - mu) / sd
+    sign = np.where(np.arange(M) % 2 == 0, 1.0, -1.0)
+    spread = 0.5 + (np.arange(M) % 7) / 7.0
+    X = (sign * ratio * spread + spread * z).astype(np.float32)
+    _, _, rcov = orc.covariance(X, want_y=False)
+    _, _, _, rcorr = orc.correlation(X, eps=0.1, want_y=False)
+    for corr in (False, True):
+        _, mean, std, out = run_stats(li, X, corr=corr)
+        _, _, fout = run_fused(li, X, corr=corr)
+        ref = rcorr if corr else rcov
+        e_unfused, e_fused = normwise(out, ref), normwise(fout, ref)
+        say("   %s: unfused %.3e fused %.3e" % ("corr" if corr else "cov", e_unfused, e_fused))
+        assert e_unfused < TOL_FP32
+        assert e_fused < TOL_FP32
