@@ -151,6 +151,23 @@ li_status li_correlation(int64_t M, int64_t N, double eps, const float *data,
                          float *data_out, double *mean, double *stddev, float *corr,
                          void *workspace, size_t workspace_bytes, li_stream stream);
 
+/* Covariance that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments, rules and results as
+ * li_covariance (bitwise the same outputs), without the workspace: the
+ * statistics and contraction partials live in a fixed device array of
+ * LI_NOALLOC_SCRATCH_BYTES compiled into the library, one per GPU, held until
+ * the process ends.  The call allocates no memory (no hipMalloc, no library
+ * allocation); its array's device address is looked up once per device on
+ * the first call there.  A problem whose partials need more than the array
+ * holds is rejected with LI_ERR_WORKSPACE before anything is launched (at
+ * 2048 features x 4096 samples it uses about 36 MiB).  Every call on one GPU
+ * shares the array: calls that can overlap on one GPU (different streams, or
+ * several host threads) race and must be ordered by the caller. */
+#define LI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+li_status li_covariance_noalloc(int64_t M, int64_t N, const float *data, float *data_out,
+                                double *mean, float *cov, li_stream stream);
+
 /* Covariance and correlation with the centring fused into the contraction
  * (the kernel fusion of Sec. VII-B, which keeps dataflow between kernels out
  * of global memory): the symmetric contraction reads `data` and centres (or

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 
 SOURCES = ["validate.cpp", "tune.cpp", "api.cpp", "gemm_f32.hip", "stats.hip", "gemm_lp.hip",
            "grouped.hip", "gemm_forms.hip", "symm_rows.hip",
-           "matvec.hip", "cov_fused.hip"]
+           "matvec.hip", "cov_fused.hip", "noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",

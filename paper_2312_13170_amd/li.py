@@ -77,6 +77,7 @@ _SIGS = {
     "li_stats_workspace_bytes": ([_i64, _i64], _sz),
     "li_covariance": ([_i64, _i64, _p, _p, _p, _p, _p, _sz, _p], _i32),
     "li_correlation": ([_i64, _i64, _f64, _p, _p, _p, _p, _p, _p, _sz, _p], _i32),
+    "li_covariance_noalloc": ([_i64, _i64, _p, _p, _p, _p, _p], _i32),
     "li_covariance_fused": ([_i64, _i64, _p, _p, _p, _p, _sz, _p], _i32),
     "li_correlation_fused": ([_i64, _i64, _f64, _p, _p, _p, _p, _p, _sz, _p], _i32),
     "li_round16": ([_i64, _p, _p, _p, _i32, _p], _i32),
@@ -242,6 +243,14 @@ def li_correlation(M, N, eps, data, data_out, mean, stddev, corr, workspace,
     _check(_lib.li_correlation(M, N, eps, _ptr(data), _ptr(data_out), _ptr(mean), _ptr(stddev),
                                _ptr(corr), _ptr(workspace), _ws_bytes(workspace, workspace_bytes),
                                _stream(stream)))
+
+
+LI_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def li_covariance_noalloc(M, N, data, data_out, mean, cov, stream=None) -> None:
+    _check(_lib.li_covariance_noalloc(M, N, _ptr(data), _ptr(data_out), _ptr(mean), _ptr(cov),
+                                      _stream(stream)))
 
 
 def li_covariance_fused(M, N, data, mean, cov, workspace, workspace_bytes=None,

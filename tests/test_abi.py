@@ -295,3 +295,22 @@ def test_misaligned_workspace_rejected(li):
     ws = lib.li_matvec_workspace_bytes(32, 32)
     assert lib.li_bicg(32, 32, FAKE, FAKE + 8192, FAKE + 8320, FAKE + 8448, FAKE + 8576, W + 12, ws, None) == li.LI_ERR_WORKSPACE
 
+
+
+def test_no_alloc_covariance_argument_rules(li):
+    # the covariance that allocates nothing validates like li_covariance and
+    # refuses, before touching the device, a problem whose partials would not
+    # fit its fixed array
+    lib = li._lib
+    assert li.LI_NOALLOC_SCRATCH_BYTES == 64 << 20
+    M, N = 8, 16
+    xb = 4 * M * N
+    assert lib.li_covariance_noalloc(-1, N, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 3 * xb, None) == li.LI_ERR_INVALID_SIZE
+    assert lib.li_covariance_noalloc(M, 1, FAKE, FAKE + xb, FAKE + 2 * xb, FAKE + 3 * xb, None) == li.LI_ERR_INVALID_SIZE
+    li.li_tune_force(li.LI_KERNEL_SYRK_F32, 9)  # seven split-k copies of every upper tile
+    try:
+        G = 1 << 30
+        assert lib.li_covariance_noalloc(4096, 64, FAKE, FAKE + G, FAKE + 2 * G, FAKE + 3 * G, None) == li.LI_ERR_WORKSPACE
+        assert "scratch" in li.li_last_error()
+    finally:
+        li.li_tune_force(li.LI_KERNEL_SYRK_F32, -1)
