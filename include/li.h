@@ -253,7 +253,7 @@ li_status li_round16(int64_t n, const float *x, uint16_t *hi, uint16_t *lo, li_p
 
 /* ---------------------------------------------------------------------
  * Grouped execution: many independent, uneven GEMM and covariance
- * problems in one persistent launch sequence captured as a HIP graph.
+ * problems in one HIP graph of grouped launches.
  * ------------------------------------------------------------------- */
 typedef enum { LI_PROBLEM_GEMM = 0, LI_PROBLEM_COVARIANCE = 1 } li_problem_kind;
 
@@ -272,10 +272,19 @@ typedef struct li_problem {
 
 typedef struct li_group_plan li_group_plan;
 
-/* Build a plan for `count` problems: picks a tile shape per problem from
- * the tuning table, uploads a descriptor table (the library allocates it)
- * and instantiates a HIP graph of the grouped kernels.  Pointers inside
- * the problems are captured; the caller keeps those buffers alive. */
+/* Build a plan for `count` problems: picks a shape class per problem from
+ * the tuning table (families LI_KERNEL_GROUPED_GEMM / _COV), uploads a
+ * descriptor table (the library allocates it) and instantiates a HIP graph:
+ * one contraction launch per (class, kind) over a table of every output
+ * tile of its problems sorted by decreasing work, and the covariance
+ * problems' statistics launch, on which only the covariance launches
+ * depend.  Each contraction launch has one work-group per tile, which the
+ * hardware dispatcher hands out heaviest first as compute units free up;
+ * with the environment variable LI_GROUPED_PERSIST=1 at plan creation, a
+ * resident grid walks the table instead (work-group b takes tiles b,
+ * b + grid, ...).  Either way each problem's results are bitwise those of
+ * li_group_plan_launch_loop.  Pointers inside the problems are captured;
+ * the caller keeps those buffers alive. */
 li_status li_group_plan_create(const li_problem *problems, int32_t count,
                                li_group_plan **plan);
 /* Launch the plan's graph on `stream` (asynchronous). */
@@ -290,12 +299,24 @@ void li_group_plan_destroy(li_group_plan *plan);
 /* ---------------------------------------------------------------------
  * Tile-shape tuning.  Kernel families: LI_KERNEL_GEMM_F32 (also used by
  * 2mm and 3mm), LI_KERNEL_SYRK_F32 (the covariance/correlation
- * contraction), LI_KERNEL_GEMM_LP (bf16/fp16/split products),
- * LI_KERNEL_SYRK_ROWS (syrk and syr2k).  Each family has a fixed
+ * contraction), LI_KERNEL_GEMM_LP (bf16 / fp16 products),
+ * LI_KERNEL_GEMM_LP_SPLIT (split-bf16 products; the same compiled list as
+ * LI_KERNEL_GEMM_LP, its own table entries), LI_KERNEL_SYRK_ROWS (syrk and
+ * syr2k), LI_KERNEL_GROUPED_GEMM and
+ * LI_KERNEL_GROUPED_COV (the shape class of a GEMM / covariance problem in a
+ * grouped plan, chosen when the plan is created).  Each family has a fixed
  * list of compiled tile shapes; the table maps a size bucket to one of
  * them.  The search itself (timing candidates) runs outside the library.
  * ------------------------------------------------------------------- */
-enum { LI_KERNEL_GEMM_F32 = 0, LI_KERNEL_SYRK_F32 = 1, LI_KERNEL_GEMM_LP = 2, LI_KERNEL_SYRK_ROWS = 3 };
+enum {
+    LI_KERNEL_GEMM_F32 = 0,
+    LI_KERNEL_SYRK_F32 = 1,
+    LI_KERNEL_GEMM_LP = 2,
+    LI_KERNEL_SYRK_ROWS = 3,
+    LI_KERNEL_GROUPED_GEMM = 4,
+    LI_KERNEL_GROUPED_COV = 5,
+    LI_KERNEL_GEMM_LP_SPLIT = 6
+};
 
 typedef struct li_tile_config {
     int32_t bm, bn, bk;     /* block tile and K-tile                    */

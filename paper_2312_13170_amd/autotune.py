@@ -10,7 +10,11 @@ text (li_tune_save), which li.py loads at import.
 Representative problems per bucket (bucket = bit length of max(M, N, K)):
 square GEMMs 256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of
 N = 2 M samples for M = 256 .. 2048, square syrk of order 256 .. 4096 and
-square reduced-precision GEMMs.
+square reduced-precision GEMMs.  For the grouped plans, the shape class per
+bucket is searched on plans of 64 rectangular problems of one kind with
+sizes drawn log-uniform inside the bucket (32 to 1024, the batch's range):
+each class is forced while the plan is built and the graph launch is
+timed.
 
 Usage: python -m paper_2312_13170_amd.autotune [--out PATH] [--quick]
 """
@@ -108,24 +112,98 @@ def search(kernel, cases, reps, log, passes=2):
         print(json.dumps(rec), flush=True)
 
 
+def grouped_problems(kind, bucket, count=64, seed=94):
+    """`count` problems of one kind whose sizes lie in one bucket (bit length
+    `bucket` of the largest size), drawn log-uniform in [2^(b-1), 2^b) and
+    clipped to the batch range [32, 1024]; returns the problems and the
+    buffers they point to."""
+    import numpy as np
+    lo, hi = max(32, 1 << (bucket - 1)), min(1024, (1 << bucket) - 1)
+    rng = np.random.default_rng(seed + bucket + 17 * kind)
+
+    def draw():
+        return int(min(hi, max(lo, round(float(np.exp(rng.uniform(np.log(lo), np.log(hi + 1))))))))
+
+    keep, probs = [], []
+    for t in range(count):
+        if kind == li.LI_PROBLEM_GEMM:
+            M, N, K = draw(), draw(), draw()
+            A = torch.from_numpy(synth.uniform_pm1(seed, "A%d" % t, (M, K))).cuda()
+            B = torch.from_numpy(synth.uniform_pm1(seed, "B%d" % t, (K, N))).cuda()
+            C = torch.from_numpy(synth.uniform_pm1(seed, "C%d" % t, (M, N))).cuda()
+            keep += [A, B, C]
+            probs.append(li.make_problem(kind, M, N, K, 1.5, 1.2, A, B, C))
+        else:
+            M, N = draw(), draw()
+            X = torch.from_numpy(synth.uniform_pm1(seed, "X%d" % t, (N, M))).cuda()
+            Y = torch.empty_like(X)
+            mean = torch.empty(M, dtype=torch.float64, device="cuda")
+            cov = torch.empty((M, M), device="cuda")
+            keep += [X, Y, mean, cov]
+            probs.append(li.make_problem(kind, M, N, 0, 1.0, 0.0, X, None, cov, Y, mean))
+    return probs, keep
+
+
+def search_grouped(kernel, kind, buckets, reps, log, passes=2):
+    """Shape class per size bucket for the grouped plans: a plan of problems
+    of that bucket is built with each class forced and its graph launch
+    timed."""
+    for bucket in buckets:
+        probs, keep = grouped_problems(kind, bucket)
+        n = li.li_tune_num_candidates(kernel)
+        times = {}
+        for p in range(passes):
+            for idx in (range(n) if p % 2 == 0 else range(n - 1, -1, -1)):
+                li.li_tune_force(kernel, idx)
+                plan = li.li_group_plan_create(probs)
+                li.li_tune_force(kernel, -1)
+                warm_up(plan.launch, 0.2)
+                t = time_call(plan.launch, reps)
+                plan.close()
+                times[idx] = min(times.get(idx, t), t)
+        best = min(times, key=times.get)
+        li.li_tune_set(kernel, bucket, best)
+        rec = {"kernel": kernel, "case": "grouped %s bucket %d" % ("gemm" if kind == 0 else "cov", bucket),
+               "bucket": bucket, "best": best, "candidate": li.li_tune_candidate(kernel, best),
+               "ms": {str(k): round(v, 4) for k, v in times.items()}}
+        log.append(rec)
+        print(json.dumps(rec), flush=True)
+        del keep
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--out", default=os.path.join(HERE, "tune_gfx950.txt"))
     p.add_argument("--log", default=None, help="also write the timings as JSON lines")
     p.add_argument("--quick", action="store_true", help="fewer sizes and repetitions")
+    p.add_argument("--only", default="gemm,syrk,rows,lp,grouped",
+                   help="comma list of the families to search (gemm, syrk, rows, lp, grouped); "
+                        "the table's other entries are kept as loaded")
     a = p.parse_args()
+    only = set(a.only.split(","))
     torch.cuda.set_device(0)
     li.li_init()
     reps = 3 if a.quick else 10
     log = []
-    gsizes = [512, 2048] if a.quick else [256, 512, 1024, 2048, 4096, 8192]
-    search(li.LI_KERNEL_GEMM_F32, [("gemm %d" % n, gemm_case(n)) for n in gsizes], reps, log)
-    ssizes = [512, 2048] if a.quick else [256, 512, 1024, 2048]
-    search(li.LI_KERNEL_SYRK_F32, [("cov M=%d" % m, syrk_case(m)) for m in ssizes], reps, log)
-    rsizes = [1024, 2048] if a.quick else [256, 512, 1024, 2048, 4096]
-    search(li.LI_KERNEL_SYRK_ROWS, [("syrk %d" % n, rank_case(n)) for n in rsizes], reps, log)
-    lsizes = [2048, 8192] if a.quick else [1024, 2048, 4096, 8192]
-    search(li.LI_KERNEL_GEMM_LP, [("bf16x3 %d" % n, lp_case(n, "bf16x3")) for n in lsizes], reps, log)
+    if "gemm" in only:
+        gsizes = [512, 2048] if a.quick else [256, 512, 1024, 2048, 4096, 8192]
+        search(li.LI_KERNEL_GEMM_F32, [("gemm %d" % n, gemm_case(n)) for n in gsizes], reps, log)
+    if "syrk" in only:
+        ssizes = [512, 2048] if a.quick else [256, 512, 1024, 2048]
+        search(li.LI_KERNEL_SYRK_F32, [("cov M=%d" % m, syrk_case(m)) for m in ssizes], reps, log)
+    if "rows" in only:
+        rsizes = [1024, 2048] if a.quick else [256, 512, 1024, 2048, 4096]
+        search(li.LI_KERNEL_SYRK_ROWS, [("syrk %d" % n, rank_case(n)) for n in rsizes], reps, log)
+    if "lp" in only:
+        lsizes = [2048, 8192] if a.quick else [1024, 2048, 4096, 8192]
+        search(li.LI_KERNEL_GEMM_LP, [("bf16 %d" % n, lp_case(n, "bf16")) for n in lsizes], reps, log)
+        search(li.LI_KERNEL_GEMM_LP_SPLIT, [("bf16x3 %d" % n, lp_case(n, "bf16x3")) for n in lsizes], reps,
+               log)
+    if "grouped" in only:
+        # grouped plans: the batch draws sizes in [32, 1024], buckets 6 to 11
+        gb = [7, 9, 11] if a.quick else [6, 7, 8, 9, 10, 11]
+        search_grouped(li.LI_KERNEL_GROUPED_GEMM, li.LI_PROBLEM_GEMM, gb, reps, log)
+        search_grouped(li.LI_KERNEL_GROUPED_COV, li.LI_PROBLEM_COVARIANCE, gb, reps, log)
     li.li_tune_save(a.out)
     if a.log:
         with open(a.log, "w") as f:

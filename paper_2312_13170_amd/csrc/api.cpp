@@ -148,7 +148,8 @@ li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *
         return launched(li::launch_gemm_f32(cfg, M, N, K, alpha, A, K, B, N, beta, C, N, stream),
                         "gemm_f32 launch");
     }
-    const int cfg = li::tune_pick(LI_KERNEL_GEMM_LP, M, N, K);
+    // split-bf16 stages both parts of each operand: its own table entries
+    const int cfg = li::tune_pick(p == LI_BF16X3 ? LI_KERNEL_GEMM_LP_SPLIT : LI_KERNEL_GEMM_LP, M, N, K);
     return launched(li::launch_gemm_lp(cfg, (int)p, M, N, K, alpha, A, B, beta, C, workspace, stream),
                     "gemm_lp launch");
 }

@@ -28,6 +28,8 @@ namespace li {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// four floats at a 4-byte (not necessarily 16-byte) aligned address
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // Workgroups are handed to the 8 XCDs round-robin (id % 8).  Renumber so
 // that each XCD receives one contiguous range of logical tiles: neighbouring
@@ -107,17 +109,20 @@ struct TileLoader {
                     v[i] = *reinterpret_cast<const f32x4 *>(ok ? p + gr * ld + gc : zero_src());
                 }
             } else {
+                // Rows that are not 16-byte aligned: a chunk that lies inside
+                // its row is still one 16-byte load (global loads of a dword
+                // or more need only dword alignment); only the ragged chunk
+                // at a row's end is loaded element by element.
                 const int64_t base = gr * ld + gc;
+                const bool full = rok && gc + 3 < cols;
+                f32x4 x = *reinterpret_cast<const f32x4u *>(full ? p + base : zero_src());
+                if (FILLED && !full) x = fill;
+                if (!full && rok && gc < cols) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const bool ok = rok && gc + e < cols;
-                    if (FILLED) {
-                        const float x = p[ok ? base + e : 0];
-                        v[i][e] = ok ? x : fill[e];
-                    } else {
-                        v[i][e] = *(ok ? p + base + e : zero_src());
-                    }
+                    for (int e = 0; e < 4; ++e)
+                        if (gc + e < cols) x[e] = p[base + e];
                 }
+                v[i] = x;
             }
         }
     }

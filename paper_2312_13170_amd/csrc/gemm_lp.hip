@@ -201,7 +201,13 @@ __device__ __forceinline__ int swz(int r, int c)
 // LAYOUT 1: rows of BK elements with XOR-swizzled 16-byte chunks;
 // LAYOUT 2: rows padded by 16 bytes, chunks in place;
 // LAYOUT 3: LAYOUT 1 filled by direct HBM-to-LDS loads into a ring of
-// stages (gemm_lp_dma_kernel).
+// stages (gemm_lp_dma_kernel);
+// LAYOUT 4: LAYOUT 3 with the matrix-core operands of the next 16-wide k
+// step read from LDS while the current step's matrix instructions run;
+// LAYOUT 5: LAYOUT 4 with the direct loads of a K-tile issued one at a time
+// between the matrix instructions of the first k step;
+// LAYOUT 6 / 7: LAYOUT 5 on a ring of four / five stages (loads three /
+// four K-tiles ahead).
 template <int BM_, int BN_, int BK_, int WM_, int WN_, int TERMS, bool FP16, int LAYOUT = 1>
 struct LpTile {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
@@ -213,7 +219,7 @@ struct LpTile {
     static constexpr bool IS_FP16 = FP16;
     static constexpr int LAYOUT_ID = LAYOUT;
     static constexpr int RS = LAYOUT == 2 ? BK + 8 : BK;  // LDS row stride (elements)
-    static_assert(LAYOUT >= 1 && LAYOUT <= 3, "unknown LDS layout");
+    static_assert(LAYOUT >= 1 && LAYOUT <= 7, "unknown LDS layout");
     // element offset of 16-byte chunk c of row r
     __device__ __forceinline__ static int off(int r, int c)
     {
@@ -427,6 +433,56 @@ __device__ __forceinline__ void lp_tile_mma(const uint16_t *As, const uint16_t *
     }
 }
 
+// Matrix-core operands of one 16-wide k step: one 16-byte LDS chunk per
+// lane for each 32-row block of A and 32-column block of B (and part).
+template <class T>
+struct LpFrag {
+    u32x4 a[T::PARTS][T::TM], b[T::PARTS][T::TN];
+};
+
+template <class T>
+__device__ __forceinline__ void lp_read_frag(LpFrag<T> &f, const uint16_t *stage, int step, int wm0,
+                                             int wn0, int l32, int hsel)
+{
+    const uint16_t *As = stage, *Bs = stage + T::PARTS * T::A_ELEMS;
+    const int cidx = 2 * step + hsel;
+#pragma unroll
+    for (int p = 0; p < T::PARTS; ++p) {
+#pragma unroll
+        for (int i = 0; i < T::TM; ++i)
+            f.a[p][i] = *reinterpret_cast<const u32x4 *>(As + p * T::A_ELEMS + T::off(wm0 + 32 * i + l32, cidx));
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j)
+            f.b[p][j] = *reinterpret_cast<const u32x4 *>(Bs + p * T::B_ELEMS + T::off(wn0 + 32 * j + l32, cidx));
+    }
+}
+
+// The matrix-core steps of one 16-wide k step (same products, same order
+// per accumulator as lp_tile_mma).
+template <class T>
+__device__ __forceinline__ void lp_mma(const LpFrag<T> &f, f32x16 (&acc)[T::TM][T::TN])
+{
+#pragma unroll
+    for (int i = 0; i < T::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::TN; ++j) {
+            if (T::IS_FP16) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(f16x8, f.a[0][i]), __builtin_bit_cast(f16x8, f.b[0][j]), acc[i][j], 0, 0, 0);
+            } else {
+                if (T::NTERMS == 3) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, f.a[1][i]), __builtin_bit_cast(bf16x8, f.b[0][j]), acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, f.a[0][i]), __builtin_bit_cast(bf16x8, f.b[T::PARTS - 1][j]),
+                        acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, f.a[0][i]), __builtin_bit_cast(bf16x8, f.b[0][j]), acc[i][j], 0, 0, 0);
+            }
+        }
+}
+
 // s_waitcnt vmcnt(VM) lgkmcnt(0), expcnt untouched (gfx9 encoding)
 template <int VM>
 __device__ __forceinline__ void lp_wait_vm_lgkm0()
@@ -434,6 +490,9 @@ __device__ __forceinline__ void lp_wait_vm_lgkm0()
     static_assert(VM >= 0 && VM < 64, "vmcnt out of range");
     __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (0 << 8));
 }
+
+// s_waitcnt lgkmcnt(0) alone (vmcnt 63 and expcnt 7 do not wait)
+__device__ __forceinline__ void lp_wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // One K-tile of this wave's direct loads into `stage` (see
 // gemm_lp_dma_kernel); the sources advance by one K-tile.
@@ -463,6 +522,129 @@ __device__ __forceinline__ void lp_issue(uint16_t *stage, const uint16_t *(&pa)[
     }
 }
 
+// One accumulator block's matrix-core steps (lp_mma for block idx = i*TN+j).
+template <class T>
+__device__ __forceinline__ void lp_mma_block(const LpFrag<T> &f, f32x16 (&acc)[T::TM][T::TN], int idx)
+{
+    const int i = idx / T::TN, j = idx % T::TN;
+    if (T::IS_FP16) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+            __builtin_bit_cast(f16x8, f.a[0][i]), __builtin_bit_cast(f16x8, f.b[0][j]), acc[i][j], 0, 0, 0);
+    } else {
+        if (T::NTERMS == 3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, f.a[1][i]), __builtin_bit_cast(bf16x8, f.b[0][j]), acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, f.a[0][i]), __builtin_bit_cast(bf16x8, f.b[T::PARTS - 1][j]),
+                acc[i][j], 0, 0, 0);
+        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            __builtin_bit_cast(bf16x8, f.a[0][i]), __builtin_bit_cast(bf16x8, f.b[0][j]), acc[i][j], 0, 0, 0);
+    }
+}
+
+// One 16-byte direct HBM-to-LDS load per lane (the wave fills 1 KiB at dst).
+__device__ __forceinline__ void lp_dma16(const uint16_t *src, uint16_t *dst)
+{
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+// Direct load q (0 .. PARTS*(AW+BW)-1) of this wave's K-tile into `stage`,
+// in lp_issue's order; its source advances by one K-tile.
+template <class T, int P, int AW, int BW>
+__device__ __forceinline__ void lp_issue_one(uint16_t *stage, const uint16_t *(&pa)[P][AW],
+                                             const uint16_t *(&pb)[P][BW], int wave, int q)
+{
+    static_assert(P == T::PARTS, "one source per part");
+    const int p = q / (AW + BW), r = q % (AW + BW);
+    if (r < AW) {
+        lp_dma16(pa[p][r], stage + p * T::A_ELEMS + (wave * AW + r) * 512);
+        pa[p][r] += T::BK;
+    } else {
+        const int rb = r - AW;
+        lp_dma16(pb[p][rb], stage + T::PARTS * T::A_ELEMS + p * T::B_ELEMS + (wave * BW + rb) * 512);
+        pb[p][rb] += T::BK;
+    }
+}
+
+// lp_tile_steps with the next K-tile's direct loads (into `dst`, when DMA)
+// issued one per matrix-core block of the first k step, each pair fenced so
+// the compiler keeps the interleave: the load instructions issue while the
+// matrix cores work instead of between their groups.
+template <class T, bool NEXT, int VM, bool DMA, int AW, int BW>
+__device__ __forceinline__ void lp_tile_steps_il(LpFrag<T> (&fr)[2], const uint16_t *cur,
+                                                 const uint16_t *nxt, f32x16 (&acc)[T::TM][T::TN],
+                                                 int wm0, int wn0, int l32, int hsel, uint16_t *dst,
+                                                 const uint16_t *(&pa)[T::PARTS][AW],
+                                                 const uint16_t *(&pb)[T::PARTS][BW], int wave)
+{
+    constexpr int S = T::BK / 16;
+    constexpr int NB = T::TM * T::TN;
+    constexpr int NQ = T::PARTS * (AW + BW);
+    static_assert(S % 2 == 0, "an even number of k steps per K-tile keeps the fragment parity");
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        lp_wait_lgkm0();
+        if (s + 1 < S) {
+            lp_read_frag<T>(fr[(s + 1) & 1], cur, s + 1, wm0, wn0, l32, hsel);
+        } else if (NEXT) {
+            lp_wait_vm_lgkm0<VM>();
+            __builtin_amdgcn_s_barrier();
+            lp_read_frag<T>(fr[(s + 1) & 1], nxt, 0, wm0, wn0, l32, hsel);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (DMA && s == 0) {
+            // spread the loads evenly over the step's blocks
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                lp_mma_block<T>(fr[s & 1], acc, b);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = b * NQ / NB; q < (b + 1) * NQ / NB; ++q) lp_issue_one<T>(dst, pa, pb, wave, q);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            lp_mma<T>(fr[s & 1], acc);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// The k steps of one K-tile in `cur` with the operands of each next step
+// read before the current step's matrix instructions are issued, so the
+// LDS reads overlap the matrix cores (fr[s & 1] holds step s).  With NEXT,
+// the last step first waits for this wave's loads of the next K-tile
+// (vmcnt <= VM) and for all of this wave's LDS reads, meets the other waves
+// at the barrier (after which every wave's loads of `nxt` have landed and
+// no wave reads `cur` any more), then reads step 0 of `nxt`.
+template <class T, bool NEXT, int VM>
+__device__ __forceinline__ void lp_tile_steps(LpFrag<T> (&fr)[2], const uint16_t *cur,
+                                              const uint16_t *nxt, f32x16 (&acc)[T::TM][T::TN],
+                                              int wm0, int wn0, int l32, int hsel)
+{
+    constexpr int S = T::BK / 16;
+    static_assert(S % 2 == 0, "an even number of k steps per K-tile keeps the fragment parity");
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        // The reads of this step's operands were issued a whole step ago and
+        // have landed; waiting for them here (at no cost) tells the
+        // compiler so, and it then needs no wait on the reads issued next,
+        // which would otherwise exceed the LDS counter's range (15) for the
+        // four-wave tiles and make it wait for all of them.
+        lp_wait_lgkm0();
+        if (s + 1 < S) {
+            lp_read_frag<T>(fr[(s + 1) & 1], cur, s + 1, wm0, wn0, l32, hsel);
+        } else if (NEXT) {
+            lp_wait_vm_lgkm0<VM>();
+            __builtin_amdgcn_s_barrier();
+            lp_read_frag<T>(fr[(s + 1) & 1], nxt, 0, wm0, wn0, l32, hsel);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        lp_mma<T>(fr[s & 1], acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Direct HBM-to-LDS variant (LAYOUT 3).  The padded operands need no bounds
 // checks, so each wave's load sources are computed once and advanced by
 // one K-tile per step.  One global_load_lds_dwordx4 of a wave fills one
@@ -486,7 +668,8 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
     constexpr int TM = T::TM, TN = T::TN, PARTS = T::PARTS;
     constexpr int NW = T::NT / 64;
     // ring stages: three when they fit in LDS, else two
-    constexpr int ST = 3 * T::STAGE * 2 <= 160 * 1024 ? 3 : 2;
+    constexpr int ST = T::LAYOUT_ID == 6 ? 4 : T::LAYOUT_ID == 7 ? 5 : 3 * T::STAGE * 2 <= 160 * 1024 ? 3 : 2;
+    static_assert(ST * T::STAGE * 2 <= 160 * 1024, "the ring must fit in LDS");
     constexpr int RPI = 64 / CPR;  // rows one load instruction fills
     constexpr int A_INS = BM / RPI, B_INS = BN / RPI;  // instructions per part and tile
     static_assert(A_INS % NW == 0 && B_INS % NW == 0, "load instructions must divide among waves");
@@ -538,7 +721,127 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
     const int64_t nk = Kp / BK;
     uint16_t *s0 = lds, *s1 = lds + T::STAGE, *s2 = lds + (ST - 1) * T::STAGE;
     lp_issue<T, AW, BW>(s0, pa, pb, wave);
-    if constexpr (ST == 3) {
+    if constexpr (T::LAYOUT_ID >= 6) {
+        // Ring of ST stages, loads running ST - 1 K-tiles ahead: tile kt's
+        // stage is kt mod ST, and tile kt + ST - 1 goes into the stage of
+        // tile kt - 1 (free: every wave's reads of it ended before the
+        // barrier that closed tile kt - 1).
+        constexpr int R = ST;
+        static_assert(R >= 3 && (R - 2) * PER_TILE < 64, "ring depth within the vmcnt range");
+        auto at = [&](int i) { return lds + i * T::STAGE; };
+        auto next = [](int i) { return i + 1 == R ? 0 : i + 1; };
+        LpFrag<T> fr[2];
+        // tiles 1 .. R - 2 join tile 0 in flight
+#pragma unroll
+        for (int j = 1; j < R - 1; ++j)
+            if (j < nk) lp_issue<T, AW, BW>(at(j), pa, pb, wave);
+        if (nk >= R - 1)
+            lp_wait_vm_lgkm0<(R - 2) * PER_TILE>();
+        else
+            lp_wait_vm_lgkm0<0>();
+        __syncthreads();
+        lp_read_frag<T>(fr[0], at(0), 0, wm0, wn0, l32, hsel);
+        int c = 0, d = R - 1;  // stages of tile kt and of tile kt + R - 1
+        int64_t kt = 0;
+        for (; kt + R - 1 < nk; ++kt) {
+            // before the last step's barrier, tile kt + 1 must have landed:
+            // the R - 2 tiles issued after it may still be in flight
+            lp_tile_steps_il<T, true, (R - 2) * PER_TILE, true, AW, BW>(fr, at(c), at(next(c)), acc, wm0, wn0,
+                                                                        l32, hsel, at(d), pa, pb, wave);
+            c = next(c);
+            d = next(d);
+        }
+        for (; kt + 1 < nk; ++kt) {
+            lp_tile_steps_il<T, true, 0, false, AW, BW>(fr, at(c), at(next(c)), acc, wm0, wn0, l32, hsel, at(c),
+                                                        pa, pb, wave);
+            c = next(c);
+        }
+        lp_tile_steps_il<T, false, 0, false, AW, BW>(fr, at(c), nullptr, acc, wm0, wn0, l32, hsel, at(c), pa, pb,
+                                                     wave);
+        (void)s1;
+        (void)s2;
+    } else if constexpr (T::LAYOUT_ID == 5) {
+        LpFrag<T> fr[2];
+        if constexpr (ST == 3) {
+            if (nk > 1) {
+                lp_issue<T, AW, BW>(s1, pa, pb, wave);
+                lp_wait_vm_lgkm0<PER_TILE>();
+            } else {
+                lp_wait_vm_lgkm0<0>();
+            }
+            __syncthreads();
+            lp_read_frag<T>(fr[0], s0, 0, wm0, wn0, l32, hsel);
+            for (int64_t kt = 0; kt + 2 < nk; ++kt) {
+                // s0: tile kt, s1: tile kt + 1 (in flight), s2: free; tile
+                // kt + 2's loads go to s2 during the first k step
+                lp_tile_steps_il<T, true, PER_TILE, true, AW, BW>(fr, s0, s1, acc, wm0, wn0, l32, hsel, s2,
+                                                                  pa, pb, wave);
+                uint16_t *x = s0;
+                s0 = s1;
+                s1 = s2;
+                s2 = x;
+            }
+            if (nk > 1) {
+                lp_tile_steps_il<T, true, 0, false, AW, BW>(fr, s0, s1, acc, wm0, wn0, l32, hsel, s2, pa,
+                                                            pb, wave);
+                s0 = s1;
+            }
+        } else {
+            lp_wait_vm_lgkm0<0>();
+            __syncthreads();
+            lp_read_frag<T>(fr[0], s0, 0, wm0, wn0, l32, hsel);
+            for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+                // s1 held tile kt - 1, whose reads ended before the last
+                // barrier; tile kt + 1's loads go there during the first step
+                lp_tile_steps_il<T, true, 0, true, AW, BW>(fr, s0, s1, acc, wm0, wn0, l32, hsel, s1, pa,
+                                                           pb, wave);
+                uint16_t *x = s0;
+                s0 = s1;
+                s1 = x;
+            }
+        }
+        lp_tile_steps_il<T, false, 0, false, AW, BW>(fr, s0, nullptr, acc, wm0, wn0, l32, hsel, s2, pa, pb,
+                                                     wave);
+    } else if constexpr (T::LAYOUT_ID == 4) {
+        LpFrag<T> fr[2];
+        if constexpr (ST == 3) {
+            if (nk > 1) {
+                lp_issue<T, AW, BW>(s1, pa, pb, wave);
+                lp_wait_vm_lgkm0<PER_TILE>();
+            } else {
+                lp_wait_vm_lgkm0<0>();
+            }
+            __syncthreads();
+            lp_read_frag<T>(fr[0], s0, 0, wm0, wn0, l32, hsel);
+            for (int64_t kt = 0; kt + 2 < nk; ++kt) {
+                // s0: tile kt, s1: tile kt + 1 (in flight), s2: free
+                lp_issue<T, AW, BW>(s2, pa, pb, wave);
+                lp_tile_steps<T, true, PER_TILE>(fr, s0, s1, acc, wm0, wn0, l32, hsel);
+                uint16_t *x = s0;
+                s0 = s1;
+                s1 = s2;
+                s2 = x;
+            }
+            if (nk > 1) {
+                lp_tile_steps<T, true, 0>(fr, s0, s1, acc, wm0, wn0, l32, hsel);
+                s0 = s1;
+            }
+        } else {
+            lp_wait_vm_lgkm0<0>();
+            __syncthreads();
+            lp_read_frag<T>(fr[0], s0, 0, wm0, wn0, l32, hsel);
+            for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+                // s1 held tile kt - 1, whose reads ended before the last barrier
+                lp_issue<T, AW, BW>(s1, pa, pb, wave);
+                lp_tile_steps<T, true, 0>(fr, s0, s1, acc, wm0, wn0, l32, hsel);
+                uint16_t *x = s0;
+                s0 = s1;
+                s1 = x;
+            }
+        }
+        lp_tile_steps<T, false, 0>(fr, s0, nullptr, acc, wm0, wn0, l32, hsel);
+        (void)s2;
+    } else if constexpr (ST == 3) {
         if (nk > 1) {
             lp_issue<T, AW, BW>(s1, pa, pb, wave);
             lp_wait_vm_lgkm0<PER_TILE>();
@@ -649,7 +952,7 @@ int run_lp(const LpLayout &L, int64_t M, int64_t N, float alpha, float beta, flo
 {
     const int tiles_m = (int)((M + T::BM - 1) / T::BM);
     const int tiles_n = (int)((N + T::BN - 1) / T::BN);
-    launch_lp_tiles<T>(std::integral_constant<bool, T::LAYOUT_ID == 3>{}, L, M, N, alpha, beta, C,
+    launch_lp_tiles<T>(std::integral_constant<bool, T::LAYOUT_ID >= 3>{}, L, M, N, alpha, beta, C,
                        tiles_m, tiles_n, s);
     return (int)hipGetLastError();
 }
@@ -695,7 +998,7 @@ int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alp
     switch (cfg) {
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                    \
     case IDX:                                                                                     \
-        if (prec == 3) return run_lp<LpTile<BM, BN, (BK > 32 ? 32 : BK), WM, WN, 3, false, PF>>(L, M, N, alpha, beta, C, s); \
+        if (prec == 3) return run_lp<LpTile<BM, BN, (BK > 32 ? 32 : BK), WM, WN, 3, false, (PF > 4 ? 4 : PF)>>(L, M, N, alpha, beta, C, s); \
         if (prec == 2) return run_lp<LpTile<BM, BN, BK, WM, WN, 1, true, PF>>(L, M, N, alpha, beta, C, s); \
         return run_lp<LpTile<BM, BN, BK, WM, WN, 1, false, PF>>(L, M, N, alpha, beta, C, s);
         LI_GEMM_LP_CANDIDATES(LI_CASE)

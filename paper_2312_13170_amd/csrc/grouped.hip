@@ -15,8 +15,11 @@
 //                            same loop-internalised FP32 main loop and
 //                            epilogue as the single-problem kernels with the
 //                            tile shape chosen for its problem.
-// Node 2 depends on node 1 (covariance tiles read the centred data).
+// The covariance launches depend on node 1 (their tiles read the centred
+// data); the GEMM launches are independent of it.
 #include <hip/hip_runtime.h>
+
+#include <stdlib.h>
 
 #include <algorithm>
 #include <new>
@@ -26,14 +29,6 @@
 #include "li_internal.h"
 #include "stats_dev.h"
 #include "tiles.h"
-
-// Shape classes of the grouped execution.  Each class is one persistent
-// kernel (one graph node) whose GEMM and covariance tiles share the block
-// tile, so the kernel's registers are those of a single shape.
-// {class, GEMM candidate, covariance candidate, block tile, BK, waves_m, waves_n}
-#define LI_GROUPED_CLASSES(X)   \
-    X(0, 0, 0, 128, 32, 2, 2)   \
-    X(1, 2, 2, 64, 32, 2, 2)
 
 namespace li {
 namespace {
@@ -58,8 +53,8 @@ struct GStatBlock {
     int32_t prob, col0;
 };
 
-template <int BM, int BN, int BK, int WM, int WN, bool KMAJOR, int LOAD>
-using Tile = F32Tile<BM, BN, BK, WM, WN, KMAJOR, LOAD>;
+template <int BM, int BN, int BK, int WM, int WN, bool KMAJOR, int PF>
+using Tile = F32Tile<BM, BN, BK, WM, WN, KMAJOR, kLoadScalar, PF>;
 
 // Statistics of one covariance problem's block of kGStatCols columns: the
 // kMergeGroups thread rows each merge one group of chunk partials (chunk
@@ -123,8 +118,15 @@ __device__ __forceinline__ void gemm_tile(float *lds, const GProb &p, const GTil
     const int64_t m0 = (int64_t)td.tm * T::BM, n0 = (int64_t)td.tn * T::BN;
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
-    if (p.alpha != 0.f) T::mainloop(lds, p.A, p.K, p.B, p.N, p.M, p.N, 0, p.K, m0, n0, acc, p.vec4 != 0);
-    T::epilogue_gemm(acc, p.C, p.N, p.M, p.N, m0, n0, p.alpha, p.beta);
+    if (p.alpha != 0.f) T::mainloop(lds, p.A, p.K, p.B, p.N, p.M, p.N, 0, p.K, m0, n0, acc);
+    if (p.beta != 0.f) {
+        // the tile's C loads issued together, then one wait
+        float cv[T::TM][T::TN][16];
+        T::load_c(cv, p.C, p.N, p.M, p.N, m0, n0);
+        T::epilogue_gemm_loaded(acc, cv, p.C, p.N, p.M, p.N, m0, n0, p.alpha, p.beta);
+    } else {
+        T::epilogue_gemm(acc, p.C, p.N, p.M, p.N, m0, n0, p.alpha, 0.f);
+    }
 }
 
 template <class T>
@@ -133,42 +135,67 @@ __device__ __forceinline__ void syrk_tile(float *lds, const GProb &p, const GTil
     const int64_t m0 = (int64_t)td.tm * T::BM, n0 = (int64_t)td.tn * T::BN;
     f32x16 acc[T::TM][T::TN];
     T::zero(acc);
-    T::mainloop(lds, p.Y, p.M, p.Y, p.M, p.M, p.M, 0, p.N, m0, n0, acc, p.vec4 != 0);
+    T::mainloop(lds, p.Y, p.M, p.Y, p.M, p.M, p.M, 0, p.N, m0, n0, acc);
     T::epilogue_syrk(acc, p.C, p.M, m0, n0, 0, p.scale);
 }
 
-// Persistent kernel of one shape class: work-group b takes tiles b,
-// b + gridDim.x, ... of the class's tile table.
-template <int BT, int BK, int WM, int WN, int KIND>
+// Contraction kernel of one shape class over the class's tile table (sorted
+// by decreasing work).  PERSIST: a resident grid, work-group b takes tiles
+// b, b + gridDim.x, ...; otherwise one work-group per tile, handed out by
+// the hardware dispatcher heaviest first as compute units free up, with
+// each run of 64 table entries dealt to the eight XCDs in blocks of eight
+// consecutive entries (tiles of one problem share operand panels in L2).
+__device__ __forceinline__ int dispatch_tile(int b, int n)
+{
+    const int w = b & ~63;
+    if (w + 64 > n) return b;  // last partial window: in order
+    return w + (b & 7) * 8 + ((b >> 3) & 7);
+}
+
+template <int BT, int BK, int WM, int WN, int PF, int KIND, bool PERSIST>
 __global__ __launch_bounds__(64 * WM * WN) void grouped_contract(const GProb *__restrict__ probs,
                                                                  const GTile *__restrict__ tiles,
                                                                  int ntiles)
 {
-    // one main loop per kernel; vector or scalar loads per problem at run time
-    using G = Tile<BT, BT, BK, WM, WN, false, kLoadDynamic>;
-    using S = Tile<BT, BT, BK, WM, WN, true, kLoadDynamic>;
+    // one main loop per kernel; its loads take rows of any alignment
+    using G = Tile<BT, BT, BK, WM, WN, false, PF>;
+    using S = Tile<BT, BT, BK, WM, WN, true, PF>;
     constexpr int L1 = KIND == LI_PROBLEM_GEMM ? G::LDS_FLOATS : S::LDS_FLOATS;
     __shared__ __attribute__((aligned(16))) float lds[L1];
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (PERSIST) {
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            const GTile td = tiles[t];
+            const GProb &p = probs[td.prob];
+            if (KIND == LI_PROBLEM_GEMM)
+                gemm_tile<G>(lds, p, td);
+            else
+                syrk_tile<S>(lds, p, td);
+            __syncthreads();
+        }
+    } else {
+        const int t = dispatch_tile((int)blockIdx.x, ntiles);
+        if (t >= ntiles) return;
         const GTile td = tiles[t];
         const GProb &p = probs[td.prob];
         if (KIND == LI_PROBLEM_GEMM)
             gemm_tile<G>(lds, p, td);
         else
             syrk_tile<S>(lds, p, td);
-        __syncthreads();
     }
 }
 
 struct ShapeClass {
-    int cls, gemm_idx, syrk_idx, bt, bk, wm, wn;
-    const void *kernel[2];  // [LI_PROBLEM_GEMM], [LI_PROBLEM_COVARIANCE]
+    int cls, gemm_idx, syrk_idx, bt, bk, wm, wn, pf;
+    const void *kernel[2];   // [LI_PROBLEM_GEMM], [LI_PROBLEM_COVARIANCE]: one work-group per tile
+    const void *persist[2];  // the same on a resident grid
 };
 
-#define LI_CLASS(C, GI, SI, BT, BK, WM, WN)                                                         \
-    {C, GI, SI, BT, BK, WM, WN,                                                                     \
-     {(const void *)grouped_contract<BT, BK, WM, WN, LI_PROBLEM_GEMM>,                              \
-      (const void *)grouped_contract<BT, BK, WM, WN, LI_PROBLEM_COVARIANCE>}},
+#define LI_CLASS(C, GI, SI, BT, BK, WM, WN, PF)                                                     \
+    {C, GI, SI, BT, BK, WM, WN, PF,                                                                 \
+     {(const void *)grouped_contract<BT, BK, WM, WN, PF, LI_PROBLEM_GEMM, false>,                   \
+      (const void *)grouped_contract<BT, BK, WM, WN, PF, LI_PROBLEM_COVARIANCE, false>},            \
+     {(const void *)grouped_contract<BT, BK, WM, WN, PF, LI_PROBLEM_GEMM, true>,                    \
+      (const void *)grouped_contract<BT, BK, WM, WN, PF, LI_PROBLEM_COVARIANCE, true>}},
 const ShapeClass kClasses[] = {LI_GROUPED_CLASSES(LI_CLASS)};
 #undef LI_CLASS
 constexpr int kNumClasses = (int)(sizeof(kClasses) / sizeof(kClasses[0]));
@@ -183,20 +210,22 @@ bool shapes_consistent()
     for (const ShapeClass &c : kClasses) {
         const TileCfg &g = tune_cfg(LI_KERNEL_GEMM_F32, c.gemm_idx);
         const TileCfg &s = tune_cfg(LI_KERNEL_SYRK_F32, c.syrk_idx);
-        if (g.bm != c.bt || g.bn != c.bt || g.bk != c.bk || g.wm != c.wm || g.wn != c.wn) return false;
-        if (s.bm != c.bt || s.bn != c.bt || s.bk != c.bk || s.wm != c.wm || s.wn != c.wn) return false;
+        if (g.bm != c.bt || g.bn != c.bt || g.bk != c.bk || g.wm != c.wm || g.wn != c.wn ||
+            g.prefetch != c.pf || g.split_k != 1)
+            return false;
+        if (s.bm != c.bt || s.bn != c.bt || s.bk != c.bk || s.wm != c.wm || s.wn != c.wn ||
+            s.prefetch != c.pf || s.split_k != 1)
+            return false;
     }
     return true;
 }
 
-// Class of a problem: the tuned candidate if a class uses it, else the large
-// tile when the output has at least 256 rows and columns, else the small.
+// Class of a problem: the tuning table's entry for the grouped family of its
+// kind (forced > table > built-in heuristic).
 int pick_class(int kernel, int64_t M, int64_t N, int64_t K)
 {
-    const int want = tune_pick(kernel, M, N, K);
-    for (const ShapeClass &c : kClasses)
-        if ((kernel == LI_KERNEL_GEMM_F32 ? c.gemm_idx : c.syrk_idx) == want) return c.cls;
-    return (M >= 256 && N >= 256) ? 0 : 1;
+    const int c = tune_pick(kernel, M, N, K);
+    return c >= 0 && c < kNumClasses ? c : 0;
 }
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
@@ -328,6 +357,8 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
     if (li_status s = ensure_device()) return s;
     if (!shapes_consistent()) return fail(LI_ERR_HIP, "grouped tile shapes do not match the compiled candidates");
 
+    const char *pe = getenv("LI_GROUPED_PERSIST");
+    const bool persist = pe && pe[0] == '1';
     li_group_plan *p = new (std::nothrow) li_group_plan();
     if (!p) return fail(LI_ERR_HIP, "out of host memory");
     (void)hipGetDevice(&p->device);
@@ -353,7 +384,7 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
         g.mean = q.mean;
         int cls;
         if (q.kind == LI_PROBLEM_GEMM) {
-            cls = pick_class(LI_KERNEL_GEMM_F32, q.M, q.N, q.K);
+            cls = pick_class(LI_KERNEL_GROUPED_GEMM, q.M, q.N, q.K);
             const int bt = kClasses[cls].bt;
             g.cfg = kClasses[cls].gemm_idx;
             g.vec4 = (q.alpha == 0.f || (q.K % 4 == 0 && q.N % 4 == 0 && aligned16(q.A) && aligned16(q.B))) ? 1 : 0;
@@ -366,7 +397,7 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
                 }
             p->flops += 2.0 * q.M * q.N * q.K + 3.0 * q.M * q.N;
         } else {
-            cls = pick_class(LI_KERNEL_SYRK_F32, q.M, q.M, q.N);
+            cls = pick_class(LI_KERNEL_GROUPED_COV, q.M, q.M, q.N);
             const int bt = kClasses[cls].bt;
             g.cfg = kClasses[cls].syrk_idx;
             g.vec4 = (q.M % 4 == 0 && aligned16(q.data_out)) ? 1 : 0;
@@ -407,16 +438,20 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
         std::vector<GTile> sorted(tiles[c].size());
         for (size_t k = 0; k < order.size(); ++k) sorted[k] = tiles[c][order[k]];
         p->ntiles[c] = (int)sorted.size();
-        // persistent grid: as many work-groups as can be resident at once
         const ShapeClass &sc = kClasses[c / 2];
-        int per_cu = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sc.kernel[c % 2], 64 * sc.wm * sc.wn, 0) !=
-                hipSuccess ||
-            per_cu < 1) {
-            (void)hipGetLastError();
-            per_cu = 1;
+        if (persist) {
+            // as many work-groups as can be resident at once
+            int per_cu = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sc.persist[c % 2], 64 * sc.wm * sc.wn,
+                                                             0) != hipSuccess ||
+                per_cu < 1) {
+                (void)hipGetLastError();
+                per_cu = 1;
+            }
+            p->grid[c] = std::min(p->ntiles[c], per_cu * device_cu_count());
+        } else {
+            p->grid[c] = p->ntiles[c];
         }
-        p->grid[c] = std::min(p->ntiles[c], per_cu * device_cu_count());
         ok = up((void **)&p->d_tiles[c], sorted.data(), sorted.size() * sizeof(GTile));
     }
     p->nstat = (int)stat.size();
@@ -427,9 +462,11 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
         return fail(LI_ERR_HIP, "device allocation for the plan failed");
     }
 
-    // graph: grouped_stats -> one persistent launch per (class, kind)
+    // graph: one persistent launch per (class, kind); only the covariance
+    // launches depend on grouped_stats (they read the centred data), the
+    // GEMM launches depend on nothing
     hipError_t e = hipGraphCreate(&p->graph, 0);
-    hipGraphNode_t prev = nullptr;
+    hipGraphNode_t stat_node = nullptr;
     bool any = false;
     if (e == hipSuccess && p->nstat > 0) {
         void *args[] = {(void *)&p->d_probs, (void *)&p->d_stat};
@@ -440,9 +477,7 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
         kp.sharedMemBytes = 0;
         kp.kernelParams = args;
         kp.extra = nullptr;
-        hipGraphNode_t n = nullptr;
-        e = hipGraphAddKernelNode(&n, p->graph, nullptr, 0, &kp);
-        prev = n;
+        e = hipGraphAddKernelNode(&stat_node, p->graph, nullptr, 0, &kp);
         any = true;
     }
     for (int c = 0; c < kSlots && e == hipSuccess; ++c) {
@@ -450,15 +485,16 @@ li_status li_group_plan_create(const li_problem *problems, int32_t count, li_gro
         const ShapeClass &sc = kClasses[c / 2];
         void *args[] = {(void *)&p->d_probs, (void *)&p->d_tiles[c], (void *)&p->ntiles[c]};
         hipKernelNodeParams kp{};
-        kp.func = const_cast<void *>(sc.kernel[c % 2]);
+        kp.func = const_cast<void *>(persist ? sc.persist[c % 2] : sc.kernel[c % 2]);
         kp.gridDim = dim3((unsigned)p->grid[c]);
         kp.blockDim = dim3(64 * sc.wm * sc.wn);
         kp.sharedMemBytes = 0;
         kp.kernelParams = args;
         kp.extra = nullptr;
+        const bool after_stats = c % 2 == LI_PROBLEM_COVARIANCE && stat_node;
         hipGraphNode_t n = nullptr;
-        e = hipGraphAddKernelNode(&n, p->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-        prev = n;
+        e = hipGraphAddKernelNode(&n, p->graph, after_stats ? &stat_node : nullptr, after_stats ? 1 : 0,
+                                  &kp);
         any = true;
     }
     if (e == hipSuccess && any) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);

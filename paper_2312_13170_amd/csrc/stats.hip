@@ -78,9 +78,22 @@ __global__ __launch_bounds__(kStatThreads) void colstats_finalize(
         na = (double)(r1 - r0);
         ma = part[(s0 * 2 + 0) * M + j];
         m2a = part[(s0 * 2 + 1) * M + j];
-        for (int64_t s = s0 + 1; s < s1; ++s) {
-            chunk_rows(s, rows_per_split, N, r0, r1);
-            chan_merge(na, ma, m2a, (double)(r1 - r0), part[(s * 2 + 0) * M + j], part[(s * 2 + 1) * M + j]);
+        // the partials eight at a time: all eight loads in flight, then the
+        // merges in chunk order (not one load round trip per merge)
+        for (int64_t s = s0 + 1; s < s1; s += 8) {
+            double pm[8], pq[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (s + u < s1) {
+                    pm[u] = part[((s + u) * 2 + 0) * M + j];
+                    pq[u] = part[((s + u) * 2 + 1) * M + j];
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (s + u < s1) {
+                    chunk_rows(s + u, rows_per_split, N, r0, r1);
+                    chan_merge(na, ma, m2a, (double)(r1 - r0), pm[u], pq[u]);
+                }
         }
     }
     gn[g][c] = na;

@@ -14,6 +14,23 @@
 
 namespace li {
 
+// One row's contribution to a chunk's shifted sums (d = x - x0).
+__device__ __forceinline__ void moments_add(double d, double &s1, double &s2)
+{
+    s1 += d;
+    s2 += d * d;
+}
+
+// Chunk mean and centred sum of squares from the shifted sums of n rows.
+__device__ __forceinline__ void moments_finish(double x0, double s1, double s2, double n, double &mean,
+                                               double &m2)
+{
+    double q = s2 - s1 * (s1 / n);
+    if (q < 0.0) q = 0.0;
+    mean = x0 + s1 / n;
+    m2 = q;
+}
+
 __device__ __forceinline__ void chunk_moments(const float *col, int64_t ld, int64_t r0, int64_t r1,
                                               double &mean, double &m2)
 {
@@ -26,21 +43,10 @@ __device__ __forceinline__ void chunk_moments(const float *col, int64_t ld, int6
 #pragma unroll
         for (int u = 0; u < 8; ++u) d[u] = (double)col[(r + u) * ld] - x0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            s1 += d[u];
-            s2 += d[u] * d[u];
-        }
+        for (int u = 0; u < 8; ++u) moments_add(d[u], s1, s2);
     }
-    for (; r < r1; ++r) {
-        const double d = (double)col[r * ld] - x0;
-        s1 += d;
-        s2 += d * d;
-    }
-    const double n = (double)(r1 - r0);
-    double q = s2 - s1 * (s1 / n);
-    if (q < 0.0) q = 0.0;
-    mean = x0 + s1 / n;
-    m2 = q;
+    for (; r < r1; ++r) moments_add((double)col[r * ld] - x0, s1, s2);
+    moments_finish(x0, s1, s2, (double)(r1 - r0), mean, m2);
 }
 
 // (na, ma, m2a) <- merge with (nb, mb, m2b)

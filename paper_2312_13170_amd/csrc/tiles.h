@@ -83,11 +83,18 @@
     X(18, 128, 128, 32, 4, 4, 0, 2)          \
     X(19, 128, 128, 32, 2, 4, 0, 3)          \
     X(20, 128, 128, 32, 4, 4, 0, 4)          \
-    X(21, 64, 64, 32, 2, 2, 0, 2)
+    X(21, 64, 64, 32, 2, 2, 0, 2)            \
+    X(22, 128, 128, 32, 2, 4, 1, 3)          \
+    X(23, 64, 64, 32, 2, 2, 1, 3)
 
 // bf16 / fp16 matrix-core GEMM on pre-rounded operands; the last column is
 // the LDS layout here (1: XOR-swizzled rows, 2: rows padded by 16 bytes,
-// 3: layout 1 filled by direct HBM-to-LDS loads).
+// 3: layout 1 filled by direct HBM-to-LDS loads, 4: layout 3 with the next
+// k step's operands read from LDS while the current step's matrix
+// instructions run, 5: layout 4 with the direct loads issued between the
+// matrix instructions, 6 / 7: layout 5 on a four / five stage ring).
+// The split variant caps the layout at 4 (the interleaved loads spill its
+// registers, and its stage holds both parts, so two stages fill the LDS).
 // The split-bf16 variant caps the K-tile at 32.  Candidates 13 and 14 give
 // each of four waves a 128 x 128 block (256 accumulator registers, one wave
 // per SIMD): half the LDS fragment reads per matrix-core step of the
@@ -107,7 +114,19 @@
     X(11, 128, 256, 32, 2, 2, 1, 3)          \
     X(12, 256, 256, 64, 2, 4, 1, 3)          \
     X(13, 256, 256, 64, 2, 2, 1, 3)          \
-    X(14, 256, 256, 32, 2, 2, 1, 3)
+    X(14, 256, 256, 32, 2, 2, 1, 3)          \
+    X(15, 256, 256, 32, 2, 4, 1, 4)          \
+    X(16, 256, 256, 64, 2, 4, 1, 4)          \
+    X(17, 256, 256, 64, 2, 2, 1, 4)          \
+    X(18, 256, 256, 32, 2, 2, 1, 4)          \
+    X(19, 256, 256, 32, 2, 4, 1, 5)          \
+    X(20, 256, 256, 64, 2, 4, 1, 5)          \
+    X(21, 256, 256, 64, 2, 2, 1, 5)          \
+    X(22, 256, 256, 32, 2, 2, 1, 5)          \
+    X(23, 256, 256, 32, 2, 4, 1, 6)          \
+    X(24, 256, 256, 32, 2, 4, 1, 7)          \
+    X(25, 256, 256, 32, 2, 2, 1, 6)          \
+    X(26, 256, 256, 32, 2, 2, 1, 7)
 
 // Row-form symmetric updates (syrk A A^T, syr2k A B^T + B A^T): square block
 // tiles, operands with k contiguous.
@@ -128,3 +147,17 @@
     X(13, 128, 128, 32, 2, 4, 0, 3)          \
     X(14, 64, 64, 32, 2, 2, 0, 2)            \
     X(15, 128, 128, 32, 4, 4, 0, 4)
+
+// Shape classes of the grouped execution (grouped.hip), also the candidates
+// of the tuning families LI_KERNEL_GROUPED_GEMM / LI_KERNEL_GROUPED_COV.
+// Each class is one contraction kernel per problem kind whose tiles share
+// the block tile; the main loop keeps two K-tiles in flight with the LDS
+// operand reads pipelined across the barrier (mode 3) and loads rows of any
+// alignment with 16-byte loads.  The GEMM and covariance candidates named
+// are the single-problem candidates of the same shape, which the
+// per-instance launch loop of a plan uses.
+// {class, GEMM candidate, covariance candidate, block tile, BK, waves_m,
+//  waves_n, main-loop mode}
+#define LI_GROUPED_CLASSES(X)      \
+    X(0, 13, 22, 128, 32, 2, 4, 3) \
+    X(1, 16, 23, 64, 32, 2, 2, 3)

@@ -20,8 +20,11 @@ const TileCfg kSyrkF32[] = {LI_SYRK_F32_CANDIDATES(LI_ENTRY)};
 const TileCfg kGemmLp[] = {LI_GEMM_LP_CANDIDATES(LI_ENTRY)};
 const TileCfg kSyrkRows[] = {LI_SYRK_ROWS_CANDIDATES(LI_ENTRY)};
 #undef LI_ENTRY
+#define LI_CLASS_ENTRY(C, GI, SI, BT, BK, WM, WN, PF) {BT, BT, BK, WM, WN, 1, PF},
+const TileCfg kGrouped[] = {LI_GROUPED_CLASSES(LI_CLASS_ENTRY)};
+#undef LI_CLASS_ENTRY
 
-constexpr int kFamilies = 4;
+constexpr int kFamilies = 7;
 constexpr int kBuckets = 64;
 
 const TileCfg *family(int k, int *n)
@@ -34,11 +37,16 @@ const TileCfg *family(int k, int *n)
         *n = (int)(sizeof(kSyrkF32) / sizeof(kSyrkF32[0]));
         return kSyrkF32;
     case LI_KERNEL_GEMM_LP:
+    case LI_KERNEL_GEMM_LP_SPLIT:
         *n = (int)(sizeof(kGemmLp) / sizeof(kGemmLp[0]));
         return kGemmLp;
     case LI_KERNEL_SYRK_ROWS:
         *n = (int)(sizeof(kSyrkRows) / sizeof(kSyrkRows[0]));
         return kSyrkRows;
+    case LI_KERNEL_GROUPED_GEMM:
+    case LI_KERNEL_GROUPED_COV:
+        *n = (int)(sizeof(kGrouped) / sizeof(kGrouped[0]));
+        return kGrouped;
     default:
         *n = 0;
         return nullptr;
@@ -78,7 +86,11 @@ int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
         if (K >= 1024) return 7;
         return 9;
     }
-    if (kernel == LI_KERNEL_GEMM_LP) {
+    if (kernel == LI_KERNEL_GROUPED_GEMM || kernel == LI_KERNEL_GROUPED_COV) {
+        // the 128 class when the output has at least 256 rows and columns
+        return (M >= 256 && N >= 256) ? 0 : 1;
+    }
+    if (kernel == LI_KERNEL_GEMM_LP || kernel == LI_KERNEL_GEMM_LP_SPLIT) {
         if (ceil_div(M, 256) * ceil_div(N, 256) >= cus) return 0;
         if (ceil_div(M, 128) * ceil_div(N, 128) >= cus / 2) return 1;
         return 4;

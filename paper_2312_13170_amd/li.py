@@ -36,6 +36,7 @@ PRECISIONS = {"fp32": LI_FP32, "bf16": LI_BF16, "fp16": LI_FP16, "bf16x3": LI_BF
 
 LI_PROBLEM_GEMM, LI_PROBLEM_COVARIANCE = 0, 1
 LI_KERNEL_GEMM_F32, LI_KERNEL_SYRK_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_SYRK_ROWS = 0, 1, 2, 3
+LI_KERNEL_GROUPED_GEMM, LI_KERNEL_GROUPED_COV, LI_KERNEL_GEMM_LP_SPLIT = 4, 5, 6
 
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64

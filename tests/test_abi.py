@@ -146,7 +146,7 @@ def test_precision_enum_and_workspace(li):
 
 def test_tuning_table(li):
     for k in (li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_GEMM_LP,
-              li.LI_KERNEL_SYRK_ROWS):
+              li.LI_KERNEL_SYRK_ROWS, li.LI_KERNEL_GEMM_LP_SPLIT):
         n = li.li_tune_num_candidates(k)
         assert n >= 3
         for i in range(n):
@@ -169,6 +169,15 @@ def test_tuning_table(li):
         li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, old)
     with pytest.raises(li.LiError):
         li.li_tune_force(7, 0)
+    # the grouped families list the plans' shape classes (square tiles)
+    for k in (li.LI_KERNEL_GROUPED_GEMM, li.LI_KERNEL_GROUPED_COV):
+        n = li.li_tune_num_candidates(k)
+        assert n >= 2
+        for i in range(n):
+            c = li.li_tune_candidate(k, i)
+            assert c["bm"] == c["bn"] and c["split_k"] == 1
+        with pytest.raises(li.LiError):
+            li.li_tune_force(k, n)
 
 
 def test_group_plan_validation(li):

@@ -1,5 +1,7 @@
-"""GPU parity of the grouped execution (persistent launches in a HIP graph)
+"""GPU parity of the grouped execution (grouped launches in a HIP graph)
 against the per-instance launches and the FP64 oracle."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -108,6 +110,44 @@ def test_small_batch_all_instances(li, orc):
     for (y1, m1, c1), (y2, m2, c2_) in zip(c, c2):
         assert np.array_equal(y1, y2) and np.array_equal(m1, m2) and np.array_equal(c1, c2_)
     plan.close()
+
+
+@pytest.mark.parametrize("persist", ["0", "1"])
+def test_every_class_and_schedule(li, orc, persist):
+    # each shape class forced for both problem kinds, on the dispatched and
+    # on the resident-grid schedule: every instance against the oracle and
+    # bitwise equal to the per-instance launches
+    b = small_batch(62, 24)
+    batch = Batch(li, b, inplace_every=4)
+    n = li.li_tune_num_candidates(li.LI_KERNEL_GROUPED_GEMM)
+    assert n == li.li_tune_num_candidates(li.LI_KERNEL_GROUPED_COV) and n >= 2
+    old = os.environ.get("LI_GROUPED_PERSIST")
+    try:
+        os.environ["LI_GROUPED_PERSIST"] = persist
+        for cls in range(n):
+            say("grouped class", cls, "persist", persist)
+            li.li_tune_force(li.LI_KERNEL_GROUPED_GEMM, cls)
+            li.li_tune_force(li.LI_KERNEL_GROUPED_COV, cls)
+            plan = li.li_group_plan_create(batch.problems)
+            batch.reset()
+            plan.launch()
+            g, c = batch.results()
+            check_against_oracle(orc, batch, g, c, range(len(g)), range(len(c)))
+            batch.reset()
+            plan.launch_loop()
+            g2, c2 = batch.results()
+            for x, y in zip(g, g2):
+                assert np.array_equal(x, y), cls
+            for (y1, m1, c1), (y2, m2, c2_) in zip(c, c2):
+                assert np.array_equal(y1, y2) and np.array_equal(m1, m2) and np.array_equal(c1, c2_), cls
+            plan.close()
+    finally:
+        li.li_tune_force(li.LI_KERNEL_GROUPED_GEMM, -1)
+        li.li_tune_force(li.LI_KERNEL_GROUPED_COV, -1)
+        if old is None:
+            os.environ.pop("LI_GROUPED_PERSIST", None)
+        else:
+            os.environ["LI_GROUPED_PERSIST"] = old
 
 
 def test_grouped_1024_instances(li, orc):

@@ -109,22 +109,26 @@ def test_against_quantised_oracle(li, orc, precision, shape):
         assert normwise(out, exact) < TOL_FP32
 
 
-def test_every_tile_shape(li, orc):
+@pytest.mark.parametrize("shape", [(300, 520, 200), (70, 260, 40)])
+def test_every_tile_shape(li, orc, shape):
     # every compiled candidate in each 16-bit format (fp16 runs the f16
-    # matrix-core branch of the same kernels)
-    M, N, K = 300, 520, 200
+    # matrix-core branch of the same kernels); K = 200 gives several K-tiles,
+    # K = 40 (padded to 64) one or two, the prologue / tail cases of the rings
+    M, N, K = shape
     inp = synth.precision_inputs(M, N, K, seed=53)
     A, B = inp["A"], inp["B"]
     refs = {p: orc.gemm_quantised(A, B, p) for p in ("bf16x3", "bf16", "fp16")}
     try:
         for cfg in range(li.li_tune_num_candidates(li.LI_KERNEL_GEMM_LP)):
             for precision in ("bf16x3", "bf16", "fp16"):
-                say("lp candidate", cfg, precision)
+                say("lp candidate", cfg, precision, shape)
                 li.li_tune_force(li.LI_KERNEL_GEMM_LP, cfg)
+                li.li_tune_force(li.LI_KERNEL_GEMM_LP_SPLIT, cfg)
                 out = run_lp(li, A, B, precision)
                 assert normwise(out, refs[precision]) < 2e-6, (cfg, precision)
     finally:
         li.li_tune_force(li.LI_KERNEL_GEMM_LP, -1)
+        li.li_tune_force(li.LI_KERNEL_GEMM_LP_SPLIT, -1)
 
 
 @pytest.fixture(scope="module")
