@@ -80,6 +80,10 @@ def parse():
     p.add_argument("--stats-profile", choices=["hot", "cold"], default=None,
                    help="only run 20 covariance and 20 correlation calls at 4096 x 2048, with "
                         "(cold) or without (hot) the caches flushed before each, for kernel traces")
+    p.add_argument("--lp-profile", action="store_true",
+                   help="only run 3 + 10 bf16 products at 8192^3 (the tuned 16-bit kernel with its "
+                        "rounding pre-pass), then 3 + 10 vendor bf16 products of the rounded "
+                        "operands, for kernel traces and counters")
     p.add_argument("--rows", default=ROWS_DEFAULT, help="comma list of extra rows to measure")
     return p.parse_args()
 
@@ -172,6 +176,9 @@ def main():
 
     if args.stats_profile:
         stats_profile(args.stats_profile, torch, li, synth)
+        return
+    if args.lp_profile:
+        lp_profile(torch, li, synth)
         return
 
     checks = []  # (result name, fn(oracle) -> error dict), run by the oracle leg
@@ -408,6 +415,25 @@ def stats_profile(kind, torch, li, synth):
             fn()
         torch.cuda.synchronize()
     print(json.dumps({"stats_profile": kind, "calls": 42}), flush=True)
+
+
+def lp_profile(torch, li, synth):
+    """3 + 10 bf16 products of the 8192^3 precision workload through
+    li_gemm_ex, then 3 + 10 vendor (torch.mm) bf16 products of the same
+    operands rounded to bf16."""
+    c = synth.workload("precision_8192")
+    n = c["M"]
+    A, B = torch.from_numpy(c["A"]).cuda(), torch.from_numpy(c["B"]).cuda()
+    C = torch.empty((n, n), device="cuda")
+    ws = torch.empty(li.li_gemm_ex_workspace_bytes(n, n, n, "bf16") // 4 + 1, device="cuda")
+    for _ in range(13):
+        li.li_gemm_ex(n, n, n, 1.0, A, B, 0.0, C, "bf16", ws)
+    torch.cuda.synchronize()
+    Ab, Bb = A.bfloat16(), B.bfloat16()
+    for _ in range(13):
+        torch.mm(Ab, Bb)
+    torch.cuda.synchronize()
+    print(json.dumps({"lp_profile": "bf16 8192^3", "calls": 13}), flush=True)
 
 
 def measure_rows(args, torch, li, synth, timer, checks):

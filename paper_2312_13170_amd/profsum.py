@@ -8,10 +8,11 @@
       FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch), each scaled by
       what the same counter reads for the plain device copy of B bytes that
       the profiled program runs (the largest copy kernel dispatch)
-  profsum.py pmc DB OUT.md --kernel SUBSTR --cmd "..."
-      mean of every collected counter per dispatch for matching kernels,
-      plus matrix-core utilisation when SQ_VALU_MFMA_BUSY_CYCLES and
-      GRBM_GUI_ACTIVE are present
+  profsum.py pmc DB[,DB2] OUT.md --kernel SUBSTR [--kernel SUBSTR2] --cmd "..."
+      mean of every collected counter per dispatch for each kernel (after
+      --skip dispatches), plus matrix-core utilisation when
+      SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE are present; several
+      counter runs' databases and commands (joined by " ;; ") may be given
 
 Every summary records the command that produced the database and a hash of
 the kernel sources, so a reader can tell whether the numbers still describe
@@ -137,28 +138,35 @@ def hbm(args):
 
 
 def pmc(args):
-    con = sqlite3.connect(args.db)
-    rows = con.execute("select kernel_name, dispatch_id, counter_name, value from counters_collection "
-                       "order by dispatch_id").fetchall()
-    agg = collections.OrderedDict()
-    kname = None
-    for n, d, c, v in rows:
-        if args.kernel in n:
-            kname = n
-            agg.setdefault(c, []).append(v)
-    mean = {c: sum(v) / len(v) for c, v in agg.items()}
-    lines = ["# Counters: %s" % args.title, "", "Command: `%s`" % args.cmd, "",
-             hash_line(args.sources), "",
-             "Kernel: `%s`" % short(kname or "?", 140), "",
-             "| counter | mean per dispatch |", "|---|---|"]
-    for c, v in mean.items():
-        lines.append("| %s | %.6g |" % (c, v))
-    if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "GRBM_GUI_ACTIVE" in mean:
-        simds = args.cus * 4
-        cycles = mean["GRBM_GUI_ACTIVE"] / args.xcds
-        util = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / simds / cycles
-        lines += ["", "Matrix-core busy fraction = SQ_VALU_MFMA_BUSY_CYCLES / (%d SIMDs x "
-                  "GRBM_GUI_ACTIVE / %d XCDs) = %.3f" % (simds, args.xcds, util)]
+    """Counters per dispatch of each --kernel (the last --skip-first... none:
+    every matching dispatch after --skip of them is averaged)."""
+    lines = ["# Counters: %s" % args.title, "", "Commands (one run per counter set):", ""]
+    lines += ["    %s" % c for c in args.cmd.split(" ;; ")]
+    lines += ["", hash_line(args.sources)]
+    for db in args.db.split(","):
+        con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, dispatch_id, counter_name, value from counters_collection "
+                           "order by dispatch_id").fetchall()
+        for want in args.kernel:
+            agg = collections.OrderedDict()
+            kname = None
+            for n, d, c, v in rows:
+                if want in n:
+                    kname = n
+                    agg.setdefault(c, []).append(v)
+            agg = {c: v[args.skip:] if len(v) > args.skip else v for c, v in agg.items()}
+            mean = {c: sum(v) / len(v) for c, v in agg.items()}
+            lines += ["", "Kernel: `%s` (%d dispatches averaged)" % (
+                short(kname or "?", 140), len(next(iter(agg.values()))) if agg else 0), "",
+                "| counter | mean per dispatch |", "|---|---|"]
+            for c, v in mean.items():
+                lines.append("| %s | %.6g |" % (c, v))
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and "GRBM_GUI_ACTIVE" in mean:
+                simds = args.cus * 4
+                cycles = mean["GRBM_GUI_ACTIVE"] / args.xcds
+                util = mean["SQ_VALU_MFMA_BUSY_CYCLES"] / simds / cycles
+                lines += ["", "Matrix-core busy fraction = SQ_VALU_MFMA_BUSY_CYCLES / (%d SIMDs x "
+                          "GRBM_GUI_ACTIVE / %d XCDs) = %.3f" % (simds, args.xcds, util)]
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
@@ -179,9 +187,11 @@ def main():
     h.add_argument("--copy-bytes", type=float, default=256 * 2 ** 20)
     h.add_argument("--algorithmic", type=float, default=None)
     c = sub.add_parser("pmc")
-    c.add_argument("db")
+    c.add_argument("db", help="one database, or several joined by commas (one per counter set)")
     c.add_argument("out")
-    c.add_argument("--kernel", required=True)
+    c.add_argument("--kernel", required=True, action="append",
+                   help="kernel name substring (repeat for several kernels)")
+    c.add_argument("--skip", type=int, default=0, help="leading dispatches of each kernel left out")
     c.add_argument("--cus", type=int, default=256)
     c.add_argument("--xcds", type=int, default=8)
     for q in (t, h, c):
