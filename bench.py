@@ -11,7 +11,8 @@ HBM before timing starts.
 Printed: one JSON line with the contract fields, plus
   roofline      the dominant kernel (the FP32 GEMM launch of the step) against
                 the FP32 matrix peak: its flops over its own mean duration,
-                each launch bracketed by HIP events on its stream,
+                K launches of each of the step's two products timed back to
+                back between HIP events on their stream,
   step          the whole step's rate against the same peak (launch gaps
                 included),
   rows          the other kernels of the path (mean / median / min of 30
@@ -227,22 +228,32 @@ def main():
     flops_step = f1 + f2
     value = flops_step / (ms_step * 1e-3) / 1e9
 
-    # The dominant kernel on its own: the same two launches as the step
-    # (li_gemm with li_mm2's arguments), each bracketed by events recorded on
-    # the stream it runs on, K steps' worth; its mean launch duration is what
-    # the committed kernel trace of this command reports for it.
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
+    # The dominant kernel on its own: each of the step's two GEMM launches
+    # (li_gemm with li_mm2's arguments) repeated K times back to back between
+    # two events recorded on the stream they run on; the mean launch
+    # duration is what the committed kernel trace of this command reports
+    # for the same launches.  (Events around every single launch add their
+    # own gaps, about 4% here; they are reported as well.)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
     for i in range(args.steps):
-        ev[3 * i].record()
         li.li_gemm(NI, NJ, NK, alpha, dA, dB, 0.0, tmp)
-        ev[3 * i + 1].record()
+    e[1].record()
+    for i in range(args.steps):
         li.li_gemm(NI, NL, NJ, 1.0, tmp, dC, beta, dD)
-        ev[3 * i + 2].record()
+    e[2].record()
     torch.cuda.synchronize()
-    d1 = [ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(args.steps)]
-    d2 = [ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(args.steps)]
-    launch_ms = (sum(d1) + sum(d2)) / (2 * args.steps)
+    d1 = e[0].elapsed_time(e[1]) / args.steps
+    d2 = e[1].elapsed_time(e[2]) / args.steps
+    launch_ms = (d1 + d2) / 2
     achieved = (f1 + f2) / 2 / (launch_ms * 1e-3) / 1e12
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    for i in range(args.steps):
+        ev[2 * i].record()
+        li.li_gemm(NI, NJ, NK, alpha, dA, dB, 0.0, tmp)
+        ev[2 * i + 1].record()
+    torch.cuda.synchronize()
+    each_ms = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(args.steps)) / args.steps
 
     per_step, ms_cold = None, None
     if not args.timed_only:
@@ -278,8 +289,9 @@ def main():
                      "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": committed_traffic(),
                      "launch_us_mean": round(launch_ms * 1e3, 2),
-                     "launch_us_first_product": round(sum(d1) / len(d1) * 1e3, 2),
-                     "launch_us_second_product": round(sum(d2) / len(d2) * 1e3, 2)},
+                     "launch_us_first_product": round(d1 * 1e3, 2),
+                     "launch_us_second_product": round(d2 * 1e3, 2),
+                     "launch_us_first_product_events_each": round(each_ms * 1e3, 2)},
         "step": {"ms_mean": round(ms_step, 4),
                  "TFLOP/s": round(value / 1e3, 2),
                  "frac_fp32_mfma": round(value / 1e3 / PEAK_FP32_MFMA, 4)},

@@ -302,8 +302,17 @@ struct F32Tile {
     // PF == 4 keeps three unpadded, XOR-swizzled stages filled by direct
     // HBM-to-LDS loads (see mainloop_dma).
     static constexpr int DMA_A = BM * BK, DMA_B = BK * BN;
-    static constexpr int LDS_FLOATS =
-        PF == 4 ? 3 * (DMA_A + DMA_B) : PF == 8 ? 2 * (DMA_A + DMA_B) : 2 * (A_STAGE + B_STAGE);
+    // The fused transform (XFORM) on the direct-to-LDS loop runs on a ring
+    // of four stages (XSTAGE, mainloop_dma_xform) when each thread's chunks
+    // of a stage share their columns.
+    static constexpr bool XSTAGE = PF == 4 && XFORM != 0 && A_KMAJOR && !B_NMAJOR &&
+                                   ((BK * BM / 4) % (64 * WM * WN)) == 0 &&
+                                   ((BK * BN / 4) % (64 * WM * WN)) == 0 &&
+                                   ((64 * WM * WN) / (BM / 4)) % 8 == 0 &&
+                                   ((64 * WM * WN) / (BN / 4)) % 8 == 0;
+    static constexpr int LDS_FLOATS = PF == 4 ? (XSTAGE ? 4 : 3) * (DMA_A + DMA_B)
+                                      : PF == 8 ? 2 * (DMA_A + DMA_B)
+                                                : 2 * (A_STAGE + B_STAGE);
 
     using ALoader = TileLoader<(A_KMAJOR ? BK : BM), (A_KMAJOR ? BM : BK), NT, LOAD>;
     // transposing loads in 4 x 4 blocks when there are enough blocks for
@@ -330,6 +339,7 @@ struct F32Tile {
     struct XRegs {
         f32x4 ma, fa, mb, fb;
         float rma[TM], rfa[TM], rmb[TN], rfb[TN];
+        f32x4 sma, sfa, smb, sfb;  // XSTAGE: the columns of this thread's stage chunks
     };
 
     __device__ __forceinline__ static void load_xregs(XRegs &x, const double *mean,
@@ -359,6 +369,20 @@ struct F32Tile {
             const int64_t c = wb + 32 * t;
             x.rmb[t] = c < N ? (float)mean[c] : 0.f;
             x.rfb[t] = XFORM == 2 && c < N ? (float)factor[c] : 0.f;
+        }
+        if constexpr (XSTAGE) {
+            // the logical chunk at this thread's physical chunk of a stage
+            // (the same in every k row the thread transforms, see XSTAGE)
+            const int ka = tid / (BM / 4), kb = tid / (BN / 4);
+            const int64_t sa = m0 + 4 * ((tid % (BM / 4)) ^ swz_k(ka));
+            const int64_t sb = n0 + 4 * ((tid % (BN / 4)) ^ swz_k(kb));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                x.sma[e] = sa + e < M ? (float)mean[sa + e] : 0.f;
+                x.sfa[e] = XFORM == 2 && sa + e < M ? (float)factor[sa + e] : 0.f;
+                x.smb[e] = sb + e < N ? (float)mean[sb + e] : 0.f;
+                x.sfb[e] = XFORM == 2 && sb + e < N ? (float)factor[sb + e] : 0.f;
+            }
         }
     }
 
@@ -734,7 +758,9 @@ struct F32Tile {
     // the column transform of XFORM on operands read from LDS
     __device__ __forceinline__ static void xform_frag(Frag &f, const XRegs *x)
     {
-        if constexpr (XFORM != 0) {
+        // (XSTAGE tiles transform whole stages in LDS instead; their operand
+        // reads take the values as they are)
+        if constexpr (XFORM != 0 && !XSTAGE) {
 #pragma unroll
             for (int t = 0; t < TM; ++t)
 #pragma unroll
@@ -866,6 +892,93 @@ struct F32Tile {
         }
     }
 
+    // The column transform of XFORM applied in place to a landed stage: each
+    // thread rewrites its chunks once (y = x - m, then y *= f for XFORM 2,
+    // the FP32 operations xform_frag applies to every operand read), so the
+    // waves then read transformed operands.
+    __device__ __forceinline__ static void xform_stage(float *stage, const XRegs *x)
+    {
+        if constexpr (XSTAGE) {
+            const int tid = threadIdx.x;
+#pragma unroll
+            for (int i = 0; i < BK * BM / 4 / NT; ++i) {
+                f32x4 *q = reinterpret_cast<f32x4 *>(stage) + tid + i * NT;
+                f32x4 v = *q - x->sma;
+                if (XFORM == 2) v *= x->sfa;
+                *q = v;
+            }
+#pragma unroll
+            for (int i = 0; i < BK * BN / 4 / NT; ++i) {
+                f32x4 *q = reinterpret_cast<f32x4 *>(stage + DMA_A) + tid + i * NT;
+                f32x4 v = *q - x->smb;
+                if (XFORM == 2) v *= x->sfb;
+                *q = v;
+            }
+        }
+    }
+
+    // PF == 4 with XFORM on whole K-tiles: a ring of four stages.  While
+    // tile i is multiplied, tile i + 1 (landed) is transformed in place,
+    // tile i + 2 is in flight and tile i + 3 is issued into the stage of
+    // tile i - 1.  The barrier closing tile i follows a wait for tile i + 2,
+    // so the next tile's transform can start at once; every transform of
+    // tile i + 1 ends before that barrier, after which its operands are read.
+    __device__ __forceinline__ static void mainloop_dma_xform(float *lds, const float *A,
+                                                              int64_t lda, const float *B,
+                                                              int64_t ldb, int64_t M, int64_t N,
+                                                              int64_t kbeg, int64_t m0, int64_t n0,
+                                                              int64_t nk, f32x16 (&acc)[TM][TN],
+                                                              const XRegs *xr)
+    {
+        constexpr int SS = DMA_A + DMA_B;  // floats per stage
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const int wm0 = (wave / WN) * (BM / WM), wn0 = (wave % WN) * (BN / WN);
+        const float *pa[DMA_A_PER], *pb[DMA_B_PER];
+        dma_kmajor_ptrs<BM>(pa, A, lda, M, kbeg, m0, wave, lane);
+        dma_kmajor_ptrs<BN>(pb, B, ldb, N, kbeg, n0, wave, lane);
+        const int64_t adv_a = BK * lda, adv_b = BK * ldb;
+        auto stage = [&](int64_t i) { return lds + (int)(i & 3) * SS; };
+        // tiles 0, 1, 2 in flight; tiles 0 and 1 must land, tile 0 is
+        // transformed before the first reads
+        dma_issue(stage(0), pa, pb, adv_a, adv_b, wave);
+        if (nk > 1) dma_issue(stage(1), pa, pb, adv_a, adv_b, wave);
+        if (nk > 2) {
+            dma_issue(stage(2), pa, pb, adv_a, adv_b, wave);
+            wait_vm_lgkm0<DMA_PER_TILE>();
+        } else {
+            wait_vm_lgkm0<0>();
+        }
+        __builtin_amdgcn_s_barrier();
+        xform_stage(stage(0), xr);
+        wait_vm_lgkm0<DMA_PER_TILE>();  // (only LDS operations are waited for here)
+        __builtin_amdgcn_s_barrier();
+        Frag f;
+        read_frag_dma(stage(0), stage(0) + DMA_A, 0, wm0, wn0, lane, f);
+        for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+            float *cur = stage(kt), *nxt = stage(kt + 1);
+            if (kt + 3 < nk) dma_issue(stage(kt + 3), pa, pb, adv_a, adv_b, wave);
+            xform_stage(nxt, xr);
+            kloop_dma(cur, cur + DMA_A, f, acc, wm0, wn0, lane);
+            // tile kt + 2 must have landed for the next transform: only tile
+            // kt + 3 may still be in flight
+            if (kt + 3 < nk)
+                wait_vm_lgkm0<DMA_PER_TILE>();
+            else
+                wait_vm_lgkm0<0>();
+            __builtin_amdgcn_s_barrier();
+            Frag g;
+            read_frag_dma(nxt, nxt + DMA_A, 0, wm0, wn0, lane, g);
+            mma(f, acc);
+            f = g;
+        }
+        const float *last = stage(nk - 1);
+        kloop_dma(last, last + DMA_A, f, acc, wm0, wn0, lane);
+        mma(f, acc);
+        wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();
+    }
+
     __device__ __forceinline__ static void mainloop_dma_full(float *lds, const float *A,
                                                              int64_t lda, const float *B,
                                                              int64_t ldb, int64_t M, int64_t N,
@@ -979,8 +1092,12 @@ struct F32Tile {
                 // ring has no ragged-tile loop, and out-of-range k would not
                 // become 0 after the transform); a ragged range would be
                 // skipped rather than read past the matrix.
-                if ((kend - kbeg) % BK == 0)
-                    mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
+                if ((kend - kbeg) % BK == 0) {
+                    if constexpr (XSTAGE)
+                        mainloop_dma_xform(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
+                    else
+                        mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
+                }
             } else if ((kend - kbeg) % BK == 0) {
                 mainloop_dma_full(lds, A, lda, B, ldb, M, N, kbeg, m0, n0, nk, acc, xr);
             } else {

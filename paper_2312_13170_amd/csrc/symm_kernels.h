@@ -229,10 +229,7 @@ __global__ __launch_bounds__(T::NT) void sym_streamk_kernel(SymArgs a, float *__
     __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
     const int nb = tiles * (tiles + 1) / 2;
     const int G = gridDim.x;
-    // logical work-group: each XCD runs one contiguous block of the ranges,
-    // so its work-groups reduce neighbouring tiles (one tile row and its
-    // column panels) and share operand panels in its L2
-    const int g = xcd_remap(blockIdx.x, G);
+    const int g = blockIdx.x;
     const int64_t total = (int64_t)nb * kt;
     const int64_t beg = sk_begin(g, total, G), end = sk_begin(g + 1, total, G);
     for (int64_t it = beg; it < end;) {

@@ -85,7 +85,9 @@
     X(20, 128, 128, 32, 4, 4, 0, 4)          \
     X(21, 64, 64, 32, 2, 2, 0, 2)            \
     X(22, 128, 128, 32, 2, 4, 1, 3)          \
-    X(23, 64, 64, 32, 2, 2, 1, 3)
+    X(23, 64, 64, 32, 2, 2, 1, 3)            \
+    X(24, 128, 128, 32, 4, 4, 0, 3)          \
+    X(25, 128, 128, 32, 2, 4, 0, 4)
 
 // bf16 / fp16 matrix-core GEMM on pre-rounded operands; the last column is
 // the LDS layout here (1: XOR-swizzled rows, 2: rows padded by 16 bytes,
