@@ -109,7 +109,19 @@ __global__ __launch_bounds__(kGStatThreads) void grouped_stats(const GProb *__re
     if (!live) return;
     const double ma = smean[c];
     float *ycol = p.Y + j;
-    for (int64_t r = g; r < N; r += kMergeGroups) ycol[r * M] = centre_value(col[r * M], ma, 0.0, false);
+    // eight of this thread's rows in flight per step (data_out may be the
+    // data itself: every element is still read before it is written, by
+    // the same thread)
+    constexpr int64_t RS = kMergeGroups;  // row stride of a thread
+    int64_t r = g;
+    for (; r + 7 * RS < N; r += 8 * RS) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = col[(r + u * RS) * M];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ycol[(r + u * RS) * M] = centre_value(x[u], ma, 0.0, false);
+    }
+    for (; r < N; r += RS) ycol[r * M] = centre_value(col[r * M], ma, 0.0, false);
 }
 
 template <class T>

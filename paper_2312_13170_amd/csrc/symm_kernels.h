@@ -303,6 +303,12 @@ int run_sym(const SymArgs &a, int splits, float *ws, hipStream_t s)
     const int groups = device_cu_count() * (T::NT >= 1024 ? 1 : 2);
     const int tiles = (int)((a.n + T::BM - 1) / T::BM);
     const int nb = tiles * (tiles + 1) / 2;
+    if constexpr (T::NT % kReduceThreads != 0) {
+        // work-groups smaller than one reduce slice: one kernel, no split
+        if (splits != 1 && a.reads && a.kdim > 0) return (int)hipErrorInvalidValue;
+        hipLaunchKernelGGL((sym_kernel<T, FORM>), dim3(nb), dim3(T::NT), 0, s, a, tiles);
+        return (int)hipGetLastError();
+    } else {
     if (splits == 0 && a.reads && a.kdim > 0) {
         if (!ws) return (int)hipErrorInvalidValue;
         const int kt = (int)((a.kdim + T::BK - 1) / T::BK);
@@ -331,6 +337,7 @@ int run_sym(const SymArgs &a, int splits, float *ws, hipStream_t s)
     hipLaunchKernelGGL(sym_split_reduce_kernel<T>, dim3(nb * (T::NT / kReduceThreads)),
                        dim3(kReduceThreads), 0, s, a, (const float *)ws, tiles, splits);
     return (int)hipGetLastError();
+    }
 }
 
 }  // namespace li

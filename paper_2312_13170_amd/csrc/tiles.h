@@ -58,7 +58,8 @@
     X(46, 128, 128, 32, 2, 2, 1, 8)          \
     X(47, 256, 128, 32, 4, 2, 1, 4)          \
     X(48, 256, 128, 32, 4, 2, 1, 8)          \
-    X(49, 128, 256, 32, 2, 4, 1, 8)
+    X(49, 128, 256, 32, 2, 4, 1, 8)          \
+    X(50, 32, 32, 32, 1, 1, 1, 3)
 
 // square block tiles only (upper-triangle enumeration)
 #define LI_SYRK_F32_CANDIDATES(X)            \
@@ -87,7 +88,8 @@
     X(22, 128, 128, 32, 2, 4, 1, 3)          \
     X(23, 64, 64, 32, 2, 2, 1, 3)            \
     X(24, 128, 128, 32, 4, 4, 0, 3)          \
-    X(25, 128, 128, 32, 2, 4, 0, 4)
+    X(25, 128, 128, 32, 2, 4, 0, 4)          \
+    X(26, 32, 32, 32, 1, 1, 1, 3)
 
 // bf16 / fp16 matrix-core GEMM on pre-rounded operands; the last column is
 // the LDS layout here (1: XOR-swizzled rows, 2: rows padded by 16 bytes,
@@ -159,7 +161,9 @@
 // are the single-problem candidates of the same shape, which the
 // per-instance launch loop of a plan uses.
 // {class, GEMM candidate, covariance candidate, block tile, BK, waves_m,
-//  waves_n, main-loop mode}
+//  waves_n, main-loop mode}.  The 32 tile (one wave) wastes less of small
+// problems on padding.
 #define LI_GROUPED_CLASSES(X)      \
     X(0, 13, 22, 128, 32, 2, 4, 3) \
-    X(1, 16, 23, 64, 32, 2, 2, 3)
+    X(1, 16, 23, 64, 32, 2, 2, 3)  \
+    X(2, 50, 26, 32, 32, 1, 1, 3)
