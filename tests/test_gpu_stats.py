@@ -98,10 +98,10 @@ def test_against_oracle(li, orc, N, M, inplace):
 
 # M = 301: an odd order, so the FP64 statistics part of the workspace is not
 # a multiple of 16 bytes before rounding; the split and stream-K candidates
-# put their 16-byte partials after it
-@pytest.mark.parametrize("M", [300, 301])
-def test_every_tile_shape(li, orc, M):
-    N = 333
+# put their 16-byte partials after it.  N = 320: whole K-tiles, so the
+# two-stage-ring candidates run their own loop (ragged N falls back).
+@pytest.mark.parametrize("M,N", [(300, 333), (301, 333), (300, 320)])
+def test_every_tile_shape(li, orc, M, N):
     X = synth.stats_inputs(N, M, seed=43)["data"]
     _, _, rcov = orc.covariance(X, want_y=False)
     try:
