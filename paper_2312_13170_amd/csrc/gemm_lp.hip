@@ -2,14 +2,18 @@
 // with FP32 accumulation, and the split-bf16 three-product scheme.
 //
 // Two steps, both on the caller's stream:
-//  1. Rounding pre-pass (HBM-bound).  A (M x K) is rounded row by row into
-//     Ah[Mp][Kp]; B (K x N) is rounded and transposed into Bh[Np][Kp], so
-//     both operands are k-contiguous, the layout the 32x32x16 matrix-core
-//     step reads with one 16-byte LDS load per lane.  For split-bf16 the
-//     residuals Al = bf16(A - Ah), Bl = bf16(B - Bh) are written beside
-//     them; A - Ah is exact in FP32 (Sterbenz).  Mp, Np are padded to
-//     multiples of 256 and Kp to a multiple of 64 with zeros, so the main
-//     loop needs no bounds checks.
+//  1. Rounding pre-pass (HBM-bound).  A (M x K) is rounded into Ah and B
+//     (K x N) rounded and transposed into Bh, both k-contiguous (the layout
+//     the 32x32x16 matrix-core step reads with one 16-byte LDS load per
+//     lane) and k-blocked: blocks of 32 k values, each block holding all
+//     Mp (Np) rows of 64 bytes one after the other, so element (r, k) is at
+//     ((k / 32) * Mp + r) * 32 + k % 32.  One K-tile of a block tile is then
+//     one contiguous piece of memory, which the direct-to-LDS loads read as
+//     whole cache lines (row-major [Mp][Kp] gave 64-byte pieces 2 Kp bytes
+//     apart).  For split-bf16 the residuals Al = bf16(A - Ah),
+//     Bl = bf16(B - Bh) are written beside them; A - Ah is exact in FP32
+//     (Sterbenz).  Mp, Np are padded to multiples of 256 and Kp to a
+//     multiple of 64 with zeros, so the main loop needs no bounds checks.
 //  2. Loop-internalised GEMM (Sec. VI-C): K-tiles of every operand term go
 //     through double-buffered LDS, accumulation stays in matrix-core
 //     registers, C = alpha*acc + beta*C once at the end.
@@ -45,6 +49,14 @@ constexpr int64_t kPadMN = 256;
 constexpr int64_t kPadK = 64;
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// k values per block of the pre-pass layout, and the offset of element
+// (r, k) of an operand with P padded rows
+constexpr int64_t kKB = 32;
+__host__ __device__ __forceinline__ int64_t blk_off(int64_t r, int64_t k, int64_t P)
+{
+    return ((k / kKB) * P + r) * kKB + k % kKB;
+}
 
 // ---------------------------------------------------------------- rounding
 // float -> bfloat16 bits, round to nearest even; NaN stays a quiet NaN.
@@ -89,46 +101,51 @@ __global__ __launch_bounds__(256) void round16_kernel(const float *__restrict__ 
     }
 }
 
-// A (M x K, row-major FP32) -> hi/lo [Mp][Kp], zero padded.  One thread
-// writes 8 consecutive k of one row (16 bytes per output array).
+// A (M x K, row-major FP32) -> hi/lo in the k-blocked layout, zero padded.
+// A work-group rounds a tile of 16 rows x 128 k: thread t takes 8
+// consecutive k (one 16-byte output piece) of row t / 16, so a wave reads 4
+// row pieces of 512 bytes and the tile's 16 rows of one k block (1 KiB) are
+// contiguous in the output.
+constexpr int kRoundRows = 16, kRoundK = 128;
+
 __global__ __launch_bounds__(256) void round_rows_kernel(const float *__restrict__ A, int64_t M,
                                                          int64_t K, int64_t Mp, int64_t Kp,
                                                          uint16_t *__restrict__ hi,
                                                          uint16_t *__restrict__ lo, int prec,
                                                          int vec4)
 {
-    const int64_t cpr = Kp / 8;
-    const int64_t total = Mp * cpr;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += stride) {
-        const int64_t r = c / cpr, k0 = (c % cpr) * 8;
-        float v[8];
-        if (r < M && vec4 && k0 + 8 <= K) {
-            const f32x4 a = *reinterpret_cast<const f32x4 *>(A + r * K + k0);
-            const f32x4 b = *reinterpret_cast<const f32x4 *>(A + r * K + k0 + 4);
-            v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
-            v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
-        } else {
+    const int64_t tiles_k = (Kp + kRoundK - 1) / kRoundK;
+    const int64_t r = (int64_t)(blockIdx.x / tiles_k) * kRoundRows + threadIdx.x / 16;
+    const int64_t k0 = (int64_t)(blockIdx.x % tiles_k) * kRoundK + (threadIdx.x % 16) * 8;
+    if (r >= Mp || k0 >= Kp) return;
+    float v[8];
+    if (r < M && vec4 && k0 + 8 <= K) {
+        const f32x4 a = *reinterpret_cast<const f32x4 *>(A + r * K + k0);
+        const f32x4 b = *reinterpret_cast<const f32x4 *>(A + r * K + k0 + 4);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+        v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
+    } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (r < M && k0 + e < K) ? A[r * K + k0 + e] : 0.f;
-        }
-        u32x4 ph, pl;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            uint32_t h0, l0, h1, l1;
-            split_value(v[2 * e], prec, h0, l0);
-            split_value(v[2 * e + 1], prec, h1, l1);
-            ph[e] = h0 | (h1 << 16);
-            pl[e] = l0 | (l1 << 16);
-        }
-        *reinterpret_cast<u32x4 *>(hi + r * Kp + k0) = ph;
-        if (prec == 3) *reinterpret_cast<u32x4 *>(lo + r * Kp + k0) = pl;
+        for (int e = 0; e < 8; ++e) v[e] = (r < M && k0 + e < K) ? A[r * K + k0 + e] : 0.f;
     }
+    u32x4 ph, pl;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        uint32_t h0, l0, h1, l1;
+        split_value(v[2 * e], prec, h0, l0);
+        split_value(v[2 * e + 1], prec, h1, l1);
+        ph[e] = h0 | (h1 << 16);
+        pl[e] = l0 | (l1 << 16);
+    }
+    const int64_t off = blk_off(r, k0, Mp);
+    *reinterpret_cast<u32x4 *>(hi + off) = ph;
+    if (prec == 3) *reinterpret_cast<u32x4 *>(lo + off) = pl;
 }
 
-// B (K x N, row-major FP32) -> hi/lo [Np][Kp] (transposed), zero padded.
-// 64 x 64 tiles through LDS: coalesced reads along n, coalesced writes
-// along k.
+// B (K x N, row-major FP32) -> hi/lo transposed into the k-blocked layout,
+// zero padded.  64 x 64 tiles through LDS: coalesced reads along n; the
+// tile's two k blocks are 4 KiB each in the output, written by consecutive
+// threads in memory order.
 __global__ __launch_bounds__(256) void round_transpose_kernel(const float *__restrict__ B,
                                                               int64_t K, int64_t N, int64_t Np,
                                                               int64_t Kp, uint16_t *__restrict__ hi,
@@ -164,8 +181,8 @@ __global__ __launch_bounds__(256) void round_transpose_kernel(const float *__res
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const int e = tid + i * 256;
-        const int nr = e / 8, kc = (e % 8) * 8;
+        // k block i of the tile: row nr, quarter tid % 4
+        const int nr = tid >> 2, kc = i * (int)kKB + (tid & 3) * 8;
         u32x4 ph, pl;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -175,11 +192,10 @@ __global__ __launch_bounds__(256) void round_transpose_kernel(const float *__res
             ph[q] = h0 | (h1 << 16);
             pl[q] = l0 | (l1 << 16);
         }
-        const int64_t off = (n0 + nr) * Kp + k0 + kc;
+        const int64_t off = blk_off(n0 + nr, k0 + kc, Np);
         *reinterpret_cast<u32x4 *>(hi + off) = ph;
         if (prec == 3) *reinterpret_cast<u32x4 *>(lo + off) = pl;
     }
-    (void)Np;
 }
 
 // ---------------------------------------------------------------- GEMM
@@ -240,10 +256,10 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restri
                                                         const uint16_t *__restrict__ Al,
                                                         const uint16_t *__restrict__ Bh,
                                                         const uint16_t *__restrict__ Bl,
-                                                        int64_t Kp, float *__restrict__ C,
-                                                        int64_t M, int64_t N, float alpha,
-                                                        float beta, int tiles_m, int tiles_n,
-                                                        int group_m)
+                                                        int64_t Kp, int64_t Mp, int64_t Np,
+                                                        float *__restrict__ C, int64_t M,
+                                                        int64_t N, float alpha, float beta,
+                                                        int tiles_m, int tiles_n, int group_m)
 {
     constexpr int BM = T::BM, BN = T::BN, BK = T::BK, NT = T::NT, CPR = T::CPR;
     constexpr int TM = T::TM, TN = T::TN, PARTS = T::PARTS;
@@ -272,8 +288,8 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restri
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
     // LDS stage layout: [A parts][B parts], each part rows x BK, swizzled.
-    const uint16_t *srcA[2] = {Ah + m0 * Kp, Al ? Al + m0 * Kp : nullptr};
-    const uint16_t *srcB[2] = {Bh + n0 * Kp, Bl ? Bl + n0 * Kp : nullptr};
+    const uint16_t *srcA[2] = {Ah, Al};
+    const uint16_t *srcB[2] = {Bh, Bl};
     u32x4 ra[PARTS][T::A_CH], rb[PARTS][T::B_CH];
 
     auto gload = [&](int64_t k0) {
@@ -283,13 +299,13 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_kernel(const uint16_t *__restri
             for (int i = 0; i < T::A_CH; ++i) {
                 const int c = tid + i * NT;
                 const int r = c / CPR, cc = c % CPR;
-                ra[p][i] = *reinterpret_cast<const u32x4 *>(srcA[p] + r * Kp + k0 + cc * 8);
+                ra[p][i] = *reinterpret_cast<const u32x4 *>(srcA[p] + blk_off(m0 + r, k0 + cc * 8, Mp));
             }
 #pragma unroll
             for (int i = 0; i < T::B_CH; ++i) {
                 const int c = tid + i * NT;
                 const int r = c / CPR, cc = c % CPR;
-                rb[p][i] = *reinterpret_cast<const u32x4 *>(srcB[p] + r * Kp + k0 + cc * 8);
+                rb[p][i] = *reinterpret_cast<const u32x4 *>(srcB[p] + blk_off(n0 + r, k0 + cc * 8, Np));
             }
         }
     };
@@ -495,10 +511,12 @@ __device__ __forceinline__ void lp_wait_vm_lgkm0()
 __device__ __forceinline__ void lp_wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // One K-tile of this wave's direct loads into `stage` (see
-// gemm_lp_dma_kernel); the sources advance by one K-tile.
+// gemm_lp_dma_kernel); the sources advance by one K-tile (adv_a, adv_b
+// elements in the k-blocked layout).
 template <class T, int AW, int BW>
 __device__ __forceinline__ void lp_issue(uint16_t *stage, const uint16_t *(&pa)[T::PARTS][AW],
-                                         const uint16_t *(&pb)[T::PARTS][BW], int wave)
+                                         const uint16_t *(&pb)[T::PARTS][BW], int wave, int64_t adv_a,
+                                         int64_t adv_b)
 {
 #pragma unroll
     for (int p = 0; p < T::PARTS; ++p) {
@@ -508,7 +526,7 @@ __device__ __forceinline__ void lp_issue(uint16_t *stage, const uint16_t *(&pa)[
                 pa[p][q],
                 (__attribute__((address_space(3))) void *)(stage + p * T::A_ELEMS + (wave * AW + q) * 512),
                 16, 0, 0);
-            pa[p][q] += T::BK;
+            pa[p][q] += adv_a;
         }
 #pragma unroll
         for (int q = 0; q < BW; ++q) {
@@ -517,7 +535,7 @@ __device__ __forceinline__ void lp_issue(uint16_t *stage, const uint16_t *(&pa)[
                 (__attribute__((address_space(3))) void *)(stage + T::PARTS * T::A_ELEMS +
                                                            p * T::B_ELEMS + (wave * BW + q) * 512),
                 16, 0, 0);
-            pb[p][q] += T::BK;
+            pb[p][q] += adv_b;
         }
     }
 }
@@ -553,17 +571,18 @@ __device__ __forceinline__ void lp_dma16(const uint16_t *src, uint16_t *dst)
 // in lp_issue's order; its source advances by one K-tile.
 template <class T, int P, int AW, int BW>
 __device__ __forceinline__ void lp_issue_one(uint16_t *stage, const uint16_t *(&pa)[P][AW],
-                                             const uint16_t *(&pb)[P][BW], int wave, int q)
+                                             const uint16_t *(&pb)[P][BW], int wave, int q,
+                                             int64_t adv_a, int64_t adv_b)
 {
     static_assert(P == T::PARTS, "one source per part");
     const int p = q / (AW + BW), r = q % (AW + BW);
     if (r < AW) {
         lp_dma16(pa[p][r], stage + p * T::A_ELEMS + (wave * AW + r) * 512);
-        pa[p][r] += T::BK;
+        pa[p][r] += adv_a;
     } else {
         const int rb = r - AW;
         lp_dma16(pb[p][rb], stage + T::PARTS * T::A_ELEMS + p * T::B_ELEMS + (wave * BW + rb) * 512);
-        pb[p][rb] += T::BK;
+        pb[p][rb] += adv_b;
     }
 }
 
@@ -576,7 +595,8 @@ __device__ __forceinline__ void lp_tile_steps_il(LpFrag<T> (&fr)[2], const uint1
                                                  const uint16_t *nxt, f32x16 (&acc)[T::TM][T::TN],
                                                  int wm0, int wn0, int l32, int hsel, uint16_t *dst,
                                                  const uint16_t *(&pa)[T::PARTS][AW],
-                                                 const uint16_t *(&pb)[T::PARTS][BW], int wave)
+                                                 const uint16_t *(&pb)[T::PARTS][BW], int wave,
+                                                 int64_t adv_a, int64_t adv_b)
 {
     constexpr int S = T::BK / 16;
     constexpr int NB = T::TM * T::TN;
@@ -600,7 +620,7 @@ __device__ __forceinline__ void lp_tile_steps_il(LpFrag<T> (&fr)[2], const uint1
                 lp_mma_block<T>(fr[s & 1], acc, b);
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int q = b * NQ / NB; q < (b + 1) * NQ / NB; ++q) lp_issue_one<T>(dst, pa, pb, wave, q);
+                for (int q = b * NQ / NB; q < (b + 1) * NQ / NB; ++q) lp_issue_one<T>(dst, pa, pb, wave, q, adv_a, adv_b);
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
@@ -659,10 +679,10 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
                                                             const uint16_t *__restrict__ Al,
                                                             const uint16_t *__restrict__ Bh,
                                                             const uint16_t *__restrict__ Bl,
-                                                            int64_t Kp, float *__restrict__ C,
-                                                            int64_t M, int64_t N, float alpha,
-                                                            float beta, int tiles_m, int tiles_n,
-                                                            int group_m)
+                                                            int64_t Kp, int64_t Mp, int64_t Np,
+                                                            float *__restrict__ C, int64_t M,
+                                                            int64_t N, float alpha, float beta,
+                                                            int tiles_m, int tiles_n, int group_m)
 {
     constexpr int BM = T::BM, BN = T::BN, BK = T::BK, CPR = T::CPR;
     constexpr int TM = T::TM, TN = T::TN, PARTS = T::PARTS;
@@ -701,8 +721,8 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
     // source of each of this wave's load instructions at k = 0
-    const uint16_t *srcA[2] = {Ah + m0 * Kp, Al ? Al + m0 * Kp : nullptr};
-    const uint16_t *srcB[2] = {Bh + n0 * Kp, Bl ? Bl + n0 * Kp : nullptr};
+    const uint16_t *srcA[2] = {Ah, Al};
+    const uint16_t *srcB[2] = {Bh, Bl};
     const uint16_t *pa[PARTS][AW], *pb[PARTS][BW];
     const int rr = lane / CPR, pc = lane % CPR;
 #pragma unroll
@@ -710,17 +730,18 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
 #pragma unroll
         for (int q = 0; q < AW; ++q) {
             const int r = (wave * AW + q) * RPI + rr;
-            pa[p][q] = srcA[p] + (int64_t)r * Kp + swz<CPR>(r, pc) * 8;
+            pa[p][q] = srcA[p] + blk_off(m0 + r, swz<CPR>(r, pc) * 8, Mp);
         }
 #pragma unroll
         for (int q = 0; q < BW; ++q) {
             const int r = (wave * BW + q) * RPI + rr;
-            pb[p][q] = srcB[p] + (int64_t)r * Kp + swz<CPR>(r, pc) * 8;
+            pb[p][q] = srcB[p] + blk_off(n0 + r, swz<CPR>(r, pc) * 8, Np);
         }
     }
     const int64_t nk = Kp / BK;
+    const int64_t adv_a = BK * Mp, adv_b = BK * Np;  // one K-tile in the k-blocked layout
     uint16_t *s0 = lds, *s1 = lds + T::STAGE, *s2 = lds + (ST - 1) * T::STAGE;
-    lp_issue<T, AW, BW>(s0, pa, pb, wave);
+    lp_issue<T, AW, BW>(s0, pa, pb, wave, adv_a, adv_b);
     if constexpr (T::LAYOUT_ID >= 6) {
         // Ring of ST stages, loads running ST - 1 K-tiles ahead: tile kt's
         // stage is kt mod ST, and tile kt + ST - 1 goes into the stage of
@@ -734,7 +755,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
         // tiles 1 .. R - 2 join tile 0 in flight
 #pragma unroll
         for (int j = 1; j < R - 1; ++j)
-            if (j < nk) lp_issue<T, AW, BW>(at(j), pa, pb, wave);
+            if (j < nk) lp_issue<T, AW, BW>(at(j), pa, pb, wave, adv_a, adv_b);
         if (nk >= R - 1)
             lp_wait_vm_lgkm0<(R - 2) * PER_TILE>();
         else
@@ -747,24 +768,24 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
             // before the last step's barrier, tile kt + 1 must have landed:
             // the R - 2 tiles issued after it may still be in flight
             lp_tile_steps_il<T, true, (R - 2) * PER_TILE, true, AW, BW>(fr, at(c), at(next(c)), acc, wm0, wn0,
-                                                                        l32, hsel, at(d), pa, pb, wave);
+                                                                        l32, hsel, at(d), pa, pb, wave, adv_a, adv_b);
             c = next(c);
             d = next(d);
         }
         for (; kt + 1 < nk; ++kt) {
             lp_tile_steps_il<T, true, 0, false, AW, BW>(fr, at(c), at(next(c)), acc, wm0, wn0, l32, hsel, at(c),
-                                                        pa, pb, wave);
+                                                        pa, pb, wave, adv_a, adv_b);
             c = next(c);
         }
         lp_tile_steps_il<T, false, 0, false, AW, BW>(fr, at(c), nullptr, acc, wm0, wn0, l32, hsel, at(c), pa, pb,
-                                                     wave);
+                                                     wave, adv_a, adv_b);
         (void)s1;
         (void)s2;
     } else if constexpr (T::LAYOUT_ID == 5) {
         LpFrag<T> fr[2];
         if constexpr (ST == 3) {
             if (nk > 1) {
-                lp_issue<T, AW, BW>(s1, pa, pb, wave);
+                lp_issue<T, AW, BW>(s1, pa, pb, wave, adv_a, adv_b);
                 lp_wait_vm_lgkm0<PER_TILE>();
             } else {
                 lp_wait_vm_lgkm0<0>();
@@ -775,7 +796,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
                 // s0: tile kt, s1: tile kt + 1 (in flight), s2: free; tile
                 // kt + 2's loads go to s2 during the first k step
                 lp_tile_steps_il<T, true, PER_TILE, true, AW, BW>(fr, s0, s1, acc, wm0, wn0, l32, hsel, s2,
-                                                                  pa, pb, wave);
+                                                                  pa, pb, wave, adv_a, adv_b);
                 uint16_t *x = s0;
                 s0 = s1;
                 s1 = s2;
@@ -783,7 +804,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
             }
             if (nk > 1) {
                 lp_tile_steps_il<T, true, 0, false, AW, BW>(fr, s0, s1, acc, wm0, wn0, l32, hsel, s2, pa,
-                                                            pb, wave);
+                                                            pb, wave, adv_a, adv_b);
                 s0 = s1;
             }
         } else {
@@ -794,19 +815,19 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
                 // s1 held tile kt - 1, whose reads ended before the last
                 // barrier; tile kt + 1's loads go there during the first step
                 lp_tile_steps_il<T, true, 0, true, AW, BW>(fr, s0, s1, acc, wm0, wn0, l32, hsel, s1, pa,
-                                                           pb, wave);
+                                                           pb, wave, adv_a, adv_b);
                 uint16_t *x = s0;
                 s0 = s1;
                 s1 = x;
             }
         }
         lp_tile_steps_il<T, false, 0, false, AW, BW>(fr, s0, nullptr, acc, wm0, wn0, l32, hsel, s2, pa, pb,
-                                                     wave);
+                                                     wave, adv_a, adv_b);
     } else if constexpr (T::LAYOUT_ID == 4) {
         LpFrag<T> fr[2];
         if constexpr (ST == 3) {
             if (nk > 1) {
-                lp_issue<T, AW, BW>(s1, pa, pb, wave);
+                lp_issue<T, AW, BW>(s1, pa, pb, wave, adv_a, adv_b);
                 lp_wait_vm_lgkm0<PER_TILE>();
             } else {
                 lp_wait_vm_lgkm0<0>();
@@ -815,7 +836,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
             lp_read_frag<T>(fr[0], s0, 0, wm0, wn0, l32, hsel);
             for (int64_t kt = 0; kt + 2 < nk; ++kt) {
                 // s0: tile kt, s1: tile kt + 1 (in flight), s2: free
-                lp_issue<T, AW, BW>(s2, pa, pb, wave);
+                lp_issue<T, AW, BW>(s2, pa, pb, wave, adv_a, adv_b);
                 lp_tile_steps<T, true, PER_TILE>(fr, s0, s1, acc, wm0, wn0, l32, hsel);
                 uint16_t *x = s0;
                 s0 = s1;
@@ -832,7 +853,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
             lp_read_frag<T>(fr[0], s0, 0, wm0, wn0, l32, hsel);
             for (int64_t kt = 0; kt + 1 < nk; ++kt) {
                 // s1 held tile kt - 1, whose reads ended before the last barrier
-                lp_issue<T, AW, BW>(s1, pa, pb, wave);
+                lp_issue<T, AW, BW>(s1, pa, pb, wave, adv_a, adv_b);
                 lp_tile_steps<T, true, 0>(fr, s0, s1, acc, wm0, wn0, l32, hsel);
                 uint16_t *x = s0;
                 s0 = s1;
@@ -843,7 +864,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
         (void)s2;
     } else if constexpr (ST == 3) {
         if (nk > 1) {
-            lp_issue<T, AW, BW>(s1, pa, pb, wave);
+            lp_issue<T, AW, BW>(s1, pa, pb, wave, adv_a, adv_b);
             lp_wait_vm_lgkm0<PER_TILE>();
         } else {
             lp_wait_vm_lgkm0<0>();
@@ -851,7 +872,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
         __syncthreads();
         for (int64_t kt = 0; kt + 2 < nk; ++kt) {
             // s0: tile kt, s1: tile kt + 1 (in flight), s2: free
-            lp_issue<T, AW, BW>(s2, pa, pb, wave);
+            lp_issue<T, AW, BW>(s2, pa, pb, wave, adv_a, adv_b);
             lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
             lp_wait_vm_lgkm0<PER_TILE>();
             __builtin_amdgcn_s_barrier();
@@ -872,7 +893,7 @@ __global__ __launch_bounds__(T::NT) void gemm_lp_dma_kernel(const uint16_t *__re
         __syncthreads();
         for (int64_t kt = 0; kt + 1 < nk; ++kt) {
             // s1 held tile kt - 1, whose reads ended before the last barrier
-            lp_issue<T, AW, BW>(s1, pa, pb, wave);
+            lp_issue<T, AW, BW>(s1, pa, pb, wave, adv_a, adv_b);
             lp_tile_mma<T>(s0, s0 + PARTS * T::A_ELEMS, acc, wm0, wn0, l32, hsel);
             lp_wait_vm_lgkm0<0>();
             __builtin_amdgcn_s_barrier();
@@ -935,7 +956,7 @@ void launch_lp_tiles(std::false_type, const LpLayout &L, int64_t M, int64_t N, f
                      float beta, float *C, int tiles_m, int tiles_n, hipStream_t s)
 {
     hipLaunchKernelGGL(gemm_lp_kernel<T>, dim3(tiles_m * tiles_n), dim3(T::NT), 0, s, L.Ah, L.Al,
-                       L.Bh, L.Bl, L.Kp, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
+                       L.Bh, L.Bl, L.Kp, L.Mp, L.Np, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
 }
 
 template <class T>
@@ -943,7 +964,7 @@ void launch_lp_tiles(std::true_type, const LpLayout &L, int64_t M, int64_t N, fl
                      float beta, float *C, int tiles_m, int tiles_n, hipStream_t s)
 {
     hipLaunchKernelGGL(gemm_lp_dma_kernel<T>, dim3(tiles_m * tiles_n), dim3(T::NT), 0, s, L.Ah,
-                       L.Al, L.Bh, L.Bl, L.Kp, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
+                       L.Al, L.Bh, L.Bl, L.Kp, L.Mp, L.Np, C, M, N, alpha, beta, tiles_m, tiles_n, 8);
 }
 
 template <class T>
@@ -983,8 +1004,7 @@ int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alp
     const LpLayout L = lp_layout(M, N, K, prec, ws);
     {
         const int vec4 = (K % 4 == 0) && (((uintptr_t)A & 15) == 0);
-        int64_t blocks = (L.Mp * (L.Kp / 8) + 255) / 256;
-        if (blocks > 16384) blocks = 16384;
+        const int64_t blocks = (L.Mp / kRoundRows) * ((L.Kp + kRoundK - 1) / kRoundK);
         hipLaunchKernelGGL(round_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, M, K, L.Mp,
                            L.Kp, L.Ah, L.Al, prec, vec4);
         hipError_t e = hipGetLastError();
