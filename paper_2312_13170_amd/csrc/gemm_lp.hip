@@ -108,15 +108,14 @@ __global__ __launch_bounds__(256) void round16_kernel(const float *__restrict__ 
 // contiguous in the output.
 constexpr int kRoundRows = 16, kRoundK = 128;
 
-__global__ __launch_bounds__(256) void round_rows_kernel(const float *__restrict__ A, int64_t M,
-                                                         int64_t K, int64_t Mp, int64_t Kp,
-                                                         uint16_t *__restrict__ hi,
-                                                         uint16_t *__restrict__ lo, int prec,
-                                                         int vec4)
+__device__ __forceinline__ void round_rows_tile(int64_t tile, const float *__restrict__ A, int64_t M,
+                                                int64_t K, int64_t Mp, int64_t Kp,
+                                                uint16_t *__restrict__ hi, uint16_t *__restrict__ lo,
+                                                int prec, int vec4)
 {
     const int64_t tiles_k = (Kp + kRoundK - 1) / kRoundK;
-    const int64_t r = (int64_t)(blockIdx.x / tiles_k) * kRoundRows + threadIdx.x / 16;
-    const int64_t k0 = (int64_t)(blockIdx.x % tiles_k) * kRoundK + (threadIdx.x % 16) * 8;
+    const int64_t r = (tile / tiles_k) * kRoundRows + threadIdx.x / 16;
+    const int64_t k0 = (tile % tiles_k) * kRoundK + (threadIdx.x % 16) * 8;
     if (r >= Mp || k0 >= Kp) return;
     float v[8];
     if (r < M && vec4 && k0 + 8 <= K) {
@@ -146,14 +145,13 @@ __global__ __launch_bounds__(256) void round_rows_kernel(const float *__restrict
 // zero padded.  64 x 64 tiles through LDS: coalesced reads along n; the
 // tile's two k blocks are 4 KiB each in the output, written by consecutive
 // threads in memory order.
-__global__ __launch_bounds__(256) void round_transpose_kernel(const float *__restrict__ B,
-                                                              int64_t K, int64_t N, int64_t Np,
-                                                              int64_t Kp, uint16_t *__restrict__ hi,
-                                                              uint16_t *__restrict__ lo, int prec,
-                                                              int vec4)
+__device__ __forceinline__ void round_transpose_tile(int64_t nb, int64_t kb, const float *__restrict__ B,
+                                                     int64_t K, int64_t N, int64_t Np,
+                                                     uint16_t *__restrict__ hi,
+                                                     uint16_t *__restrict__ lo, int prec, int vec4)
 {
     __shared__ float t[64][65];
-    const int64_t n0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 64;
+    const int64_t n0 = nb * 64, k0 = kb * 64;
     const int tid = threadIdx.x;
     if (vec4) {
         // 16-byte loads (N a multiple of 4, B 16-byte aligned): four per thread
@@ -195,6 +193,27 @@ __global__ __launch_bounds__(256) void round_transpose_kernel(const float *__res
         const int64_t off = blk_off(n0 + nr, k0 + kc, Np);
         *reinterpret_cast<u32x4 *>(hi + off) = ph;
         if (prec == 3) *reinterpret_cast<u32x4 *>(lo + off) = pl;
+    }
+}
+
+// Both operands in one launch: work-groups [0, ablocks) round tiles of A,
+// the rest transpose-and-round 64 x 64 tiles of B (nbn tiles per k row).
+struct RoundArgs {
+    const float *A, *B;
+    int64_t M, N, K, Mp, Np, Kp;
+    uint16_t *Ah, *Al, *Bh, *Bl;
+    int prec, avec4, bvec4;
+    int64_t ablocks, nbn;
+};
+
+__global__ __launch_bounds__(256) void round_operands_kernel(RoundArgs a)
+{
+    const int64_t b = blockIdx.x;
+    if (b < a.ablocks) {
+        round_rows_tile(b, a.A, a.M, a.K, a.Mp, a.Kp, a.Ah, a.Al, a.prec, a.avec4);
+    } else {
+        const int64_t t = b - a.ablocks;
+        round_transpose_tile(t % a.nbn, t / a.nbn, a.B, a.K, a.N, a.Np, a.Bh, a.Bl, a.prec, a.bvec4);
     }
 }
 
@@ -1003,16 +1022,12 @@ int launch_gemm_lp(int cfg, int prec, int64_t M, int64_t N, int64_t K, float alp
     hipStream_t s = (hipStream_t)stream;
     const LpLayout L = lp_layout(M, N, K, prec, ws);
     {
-        const int vec4 = (K % 4 == 0) && (((uintptr_t)A & 15) == 0);
-        const int64_t blocks = (L.Mp / kRoundRows) * ((L.Kp + kRoundK - 1) / kRoundK);
-        hipLaunchKernelGGL(round_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, M, K, L.Mp,
-                           L.Kp, L.Ah, L.Al, prec, vec4);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return (int)e;
-        const int bvec4 = (N % 4 == 0) && (((uintptr_t)B & 15) == 0);
-        hipLaunchKernelGGL(round_transpose_kernel, dim3((unsigned)(L.Np / 64), (unsigned)(L.Kp / 64)),
-                           dim3(256), 0, s, B, K, N, L.Np, L.Kp, L.Bh, L.Bl, prec, bvec4);
-        e = hipGetLastError();
+        RoundArgs r{A, B, M, N, K, L.Mp, L.Np, L.Kp, L.Ah, L.Al, L.Bh, L.Bl, prec,
+                    (K % 4 == 0) && (((uintptr_t)A & 15) == 0), (N % 4 == 0) && (((uintptr_t)B & 15) == 0),
+                    (L.Mp / kRoundRows) * ((L.Kp + kRoundK - 1) / kRoundK), L.Np / 64};
+        const int64_t blocks = r.ablocks + r.nbn * (L.Kp / 64);
+        hipLaunchKernelGGL(round_operands_kernel, dim3((unsigned)blocks), dim3(256), 0, s, r);
+        const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (int)e;
     }
     switch (cfg) {
