@@ -340,12 +340,20 @@ typedef struct li_tile_config {
 int32_t li_tune_num_candidates(int32_t kernel);
 li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out);
 /* Size bucket of a problem: bucket = the number of bits of max(M, N, K)
- * (0..63); problems in one bucket share a table entry. */
+ * (0..63); problems in one bucket share a table entry.  The GEMM families
+ * (LI_KERNEL_GEMM_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_GEMM_LP_SPLIT) and the
+ * row-form updates (LI_KERNEL_SYRK_ROWS) look their entry up with K = 0,
+ * i.e. by the output's size alone; the other families with all three. */
 int32_t li_tune_bucket(int64_t M, int64_t N, int64_t K);
 /* Set / get the candidate used for (kernel, bucket); -1 restores the
  * built-in default. */
 li_status li_tune_set(int32_t kernel, int32_t bucket, int32_t index);
 int32_t li_tune_get(int32_t kernel, int32_t bucket);
+/* The candidate a call of family `kernel` on an M x N x K problem uses now
+ * (the forced one, else the table entry of its bucket, else the built-in
+ * default); -1 for an unknown family or a negative size.  For the
+ * covariance family pass (M, M, N): features, features, samples. */
+int32_t li_tune_pick(int32_t kernel, int64_t M, int64_t N, int64_t K);
 /* Force one candidate for every call of a family (-1 clears): used by the
  * search to time each candidate through the ordinary entry points. */
 li_status li_tune_force(int32_t kernel, int32_t index);

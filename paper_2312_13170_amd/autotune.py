@@ -7,7 +7,9 @@ the current stream (1 warm-up, then the mean of `reps` calls); the fastest
 candidate is written to the table (li_tune_set) and the table is saved as
 text (li_tune_save), which li.py loads at import.
 
-Representative problems per bucket (bucket = bit length of max(M, N, K)):
+Representative problems per bucket (bucket = bit length of max(M, N, K);
+the GEMM and row-form families look their entry up by the output's size,
+which for the square problems searched here is the same bucket):
 square GEMMs 256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of
 N = 2 M samples for M = 256 .. 2048, square syrk of order 256 .. 4096 and
 square reduced-precision GEMMs.  For the grouped plans, the shape class per

@@ -117,7 +117,16 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
 {
     const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
     if (f >= 0) return f;
-    const int b = li_tune_bucket(M, N, K);
+    // The GEMM families and the row-form updates pick their tile by the
+    // output's size: the reduction length changes the work per tile, not
+    // how many tiles fill the GPU (a 2048 x 2048 product with K = 4096 needs
+    // the tile of 2048^3, not that of 4096^3, which leaves half the compute
+    // units idle).  Their table entries are searched on square problems, for
+    // which both rules agree.  The covariance family keeps the sample count
+    // in its bucket: its split and stream-K candidates depend on it.
+    const bool by_output = kernel == LI_KERNEL_GEMM_F32 || kernel == LI_KERNEL_GEMM_LP ||
+                           kernel == LI_KERNEL_GEMM_LP_SPLIT || kernel == LI_KERNEL_SYRK_ROWS;
+    const int b = li_tune_bucket(M, N, by_output ? 0 : K);
     const int t = g_table[kernel][b].load(std::memory_order_relaxed) - 1;
     if (t >= 0) return t;
     return heuristic(kernel, M, N, K);
@@ -177,6 +186,13 @@ int32_t li_tune_get(int32_t kernel, int32_t bucket)
     int n;
     if (!li::family(kernel, &n) || bucket < 0 || bucket >= li::kBuckets) return -1;
     return li::g_table[kernel][bucket].load() - 1;
+}
+
+int32_t li_tune_pick(int32_t kernel, int64_t M, int64_t N, int64_t K)
+{
+    int n;
+    if (!li::family(kernel, &n) || M < 0 || N < 0 || K < 0) return -1;
+    return li::tune_pick(kernel, M, N, K);
 }
 
 li_status li_tune_force(int32_t kernel, int32_t index)

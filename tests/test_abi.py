@@ -169,6 +169,32 @@ def test_tuning_table(li):
         li.li_tune_set(li.LI_KERNEL_GEMM_F32, b, old)
     with pytest.raises(li.LiError):
         li.li_tune_force(7, 0)
+    assert li.li_tune_pick(7, 8, 8, 8) == -1 and li.li_tune_pick(li.LI_KERNEL_GEMM_F32, -1, 8, 8) == -1
+
+
+def test_tile_choice_by_output_size(li):
+    # The GEMM and row-form families choose by the output's size (a long
+    # reduction does not take the tile of a larger square problem); the
+    # covariance family keeps the sample count in its bucket.
+    F, S, R = li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_SYRK_ROWS
+    b12, b13 = li.li_tune_bucket(2048, 2048, 0), li.li_tune_bucket(4096, 4096, 4096)
+    assert (b12, b13) == (12, 13)
+    old = {(k, b): li.li_tune_get(k, b) for k in (F, S, R) for b in (b12, b13)}
+    try:
+        for k in (F, S, R):
+            li.li_tune_set(k, b12, 1)
+            li.li_tune_set(k, b13, 2)
+        assert li.li_tune_pick(F, 2048, 2048, 4096) == 1
+        assert li.li_tune_pick(F, 2048, 2048, 1024) == 1
+        assert li.li_tune_pick(F, 4096, 2048, 256) == 2
+        assert li.li_tune_pick(R, 2048, 2048, 65536) == 1
+        assert li.li_tune_pick(S, 2048, 2048, 4096) == 2
+        li.li_tune_force(F, 0)
+        assert li.li_tune_pick(F, 2048, 2048, 4096) == 0
+    finally:
+        li.li_tune_force(F, -1)
+        for (k, b), v in old.items():
+            li.li_tune_set(k, b, v)
     # the grouped families list the plans' shape classes (square tiles)
     for k in (li.LI_KERNEL_GROUPED_GEMM, li.LI_KERNEL_GROUPED_COV):
         n = li.li_tune_num_candidates(k)
