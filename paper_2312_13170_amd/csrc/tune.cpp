@@ -60,39 +60,39 @@ std::atomic<int> g_forced[kFamilies];
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Built-in choice: the largest tile that still gives at least one tile per
-// compute unit (256 on MI355X), else the smallest.
+// Built-in choice for buckets the table does not hold (very large or very
+// elongated problems): the shapes the search picked at the largest sizes
+// when the output has at least one tile per compute unit (256 on MI355X),
+// else the stream-K schedule for the symmetric contractions (a long
+// reduction over few output tiles) and smaller tiles for the products.
 int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
 {
-    (void)K;
     const int64_t cus = 256;
     if (kernel == LI_KERNEL_GEMM_F32) {
-        if (ceil_div(M, 128) * ceil_div(N, 128) >= cus) return 0;
+        if (ceil_div(M, 128) * ceil_div(N, 256) >= cus) return 49;  // 128 x 256, two-stage ring
+        if (ceil_div(M, 128) * ceil_div(N, 128) >= cus) return 44;  // 128 x 128, 16 waves
         if (ceil_div(M, 128) * ceil_div(N, 64) >= cus) return 3;
         return 2;
     }
     if (kernel == LI_KERNEL_SYRK_F32) {
+        // M features (the order of the result), K samples
         const int64_t t128 = ceil_div(M, 128);
-        if (t128 * (t128 + 1) / 2 >= cus) return 0;
-        return 2;
+        if (t128 * (t128 + 1) / 2 >= cus) return 22;  // 128 x 128, eight waves
+        return K >= 1024 ? 20 : 2;                     // stream-K, 16 waves
     }
     if (kernel == LI_KERNEL_SYRK_ROWS) {
-        // M is the order of C, K the reduction length: split the reduction
-        // until the upper 128-tiles times the split cover the chip
+        // M is the order of C, K the reduction length
         const int64_t t128 = ceil_div(M, 128), up = t128 * (t128 + 1) / 2;
         if (up >= cus) return 2;
-        if (up * 2 >= cus && K >= 512) return 3;
-        if (up * 4 >= cus && K >= 1024) return 4;
-        if (K >= 1024) return 7;
-        return 9;
+        return K >= 1024 ? 15 : 9;  // stream-K, 16 waves; else 64 x 64 split
     }
     if (kernel == LI_KERNEL_GROUPED_GEMM || kernel == LI_KERNEL_GROUPED_COV) {
         // the 128 class when the output has at least 256 rows and columns
         return (M >= 256 && N >= 256) ? 0 : 1;
     }
     if (kernel == LI_KERNEL_GEMM_LP || kernel == LI_KERNEL_GEMM_LP_SPLIT) {
-        if (ceil_div(M, 256) * ceil_div(N, 256) >= cus) return 0;
-        if (ceil_div(M, 128) * ceil_div(N, 128) >= cus / 2) return 1;
+        if (ceil_div(M, 256) * ceil_div(N, 256) >= cus) return kernel == LI_KERNEL_GEMM_LP ? 23 : 12;
+        if (ceil_div(M, 128) * ceil_div(N, 128) >= cus / 2) return 9;
         return 4;
     }
     return 0;

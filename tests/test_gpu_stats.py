@@ -96,6 +96,23 @@ def test_against_oracle(li, orc, N, M, inplace):
     assert np.array_equal(corr, corr.T) and np.all(np.diag(corr) == 1.0)
 
 
+# Tall data (many more samples than variables): the size bucket lies beyond
+# the searched ones, so the built-in choice runs (stream-K over the samples).
+@pytest.mark.parametrize("N,M", [(40000, 200), (33333, 129)])
+def test_tall_data(li, orc, N, M):
+    say("stats tall", N, M)
+    assert li.li_tune_get(li.LI_KERNEL_SYRK_F32, li.li_tune_bucket(M, M, N)) == -1
+    X = synth.stats_inputs(N, M, seed=47)["data"]
+    _, mean, _, cov = run_stats(li, X, corr=False)
+    _, rmean, rcov = orc.covariance(X, want_y=False)
+    assert np.allclose(mean, rmean, rtol=1e-12, atol=1e-12)
+    assert normwise(cov, rcov) < TOL_FP32
+    assert np.array_equal(cov, cov.T)
+    _, _, _, corr = run_stats(li, X, corr=True)
+    _, _, _, rcorr = orc.correlation(X, want_y=False)
+    assert normwise(corr, rcorr) < TOL_FP32
+
+
 # M = 301: an odd order, so the FP64 statistics part of the workspace is not
 # a multiple of 16 bytes before rounding; the split and stream-K candidates
 # put their 16-byte partials after it.  N = 320: whole K-tiles, so the
