@@ -342,8 +342,9 @@ li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out);
 /* Size bucket of a problem: bucket = the number of bits of max(M, N, K)
  * (0..63); problems in one bucket share a table entry.  The GEMM families
  * (LI_KERNEL_GEMM_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_GEMM_LP_SPLIT) and the
- * row-form updates (LI_KERNEL_SYRK_ROWS) look their entry up with K = 0,
- * i.e. by the output's size alone; the other families with all three. */
+ * row-form updates (LI_KERNEL_SYRK_ROWS) look their entry up by the
+ * output's area alone, as li_tune_bucket(s, s, 0) with s = floor(sqrt(M N));
+ * the other families with all three sizes. */
 int32_t li_tune_bucket(int64_t M, int64_t N, int64_t K);
 /* Set / get the candidate used for (kernel, bucket); -1 restores the
  * built-in default. */

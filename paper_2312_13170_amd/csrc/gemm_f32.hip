@@ -68,8 +68,11 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
     switch (cfg) {
 // prefetch modes 5-7 are modes 1-3 with B transposed into LDS; the
 // direct-to-LDS modes (4: three-stage ring, 8: two-stage ring) need 16-byte
-// rows and fall back to mode 2 otherwise, mode 8 also when K is not a
-// multiple of the K-tile
+// rows and fall back to mode 2 otherwise; mode 8 runs as mode 4 (which
+// takes a ragged last K-tile; mode 2 where three stages do not fit in LDS)
+// when K is not a multiple of the K-tile
+// the three-stage ring when it fits in LDS, else the register path
+#define LI_RAGGED_DMA(BM, BN, BK) ((BM + BN) * BK * 4 * 3 <= 160 * 1024 ? 4 : 2)
 #define LI_T(BM, BN, BK, WM, WN, LOAD, PF) \
     F32Tile<BM, BN, BK, WM, WN, false, LOAD, (PF > 4 && PF < 8 ? PF - 4 : PF), false, 0, (PF > 4 && PF < 8)>
 #define LI_CASE(IDX, BM, BN, BK, WM, WN, SK, PF)                                                     \
@@ -77,13 +80,14 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
         return v4 && (PF != 8 || K % BK == 0)                                                      \
                    ? run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadVec4, PF)>(M, N, K, alpha, A, lda, B, ldb, \
                                                                       beta, C, ldc, s)             \
-                   : v4 ? run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadVec4, (PF == 8 ? 2 : PF))>(       \
+                   : v4 ? run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadVec4, (PF == 8 ? LI_RAGGED_DMA(BM, BN, BK) : PF))>( \
                               M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s)                     \
                         : run_gemm<LI_T(BM, BN, BK, WM, WN, kLoadScalar, (PF == 4 || PF == 8 ? 2 : PF))>( \
                               M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
         LI_GEMM_F32_CANDIDATES(LI_CASE)
 #undef LI_CASE
 #undef LI_T
+#undef LI_RAGGED_DMA
     default:
         return (int)hipErrorInvalidValue;
     }

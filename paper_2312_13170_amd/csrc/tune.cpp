@@ -4,6 +4,7 @@
 // "forced" candidate overrides everything for one family: the search
 // (autotune.py) forces each candidate in turn and times the ordinary entry
 // points with HIP events, then writes the winners back with li_tune_set.
+#include <math.h>
 #include <stdio.h>
 
 #include <atomic>
@@ -118,15 +119,25 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
     const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
     if (f >= 0) return f;
     // The GEMM families and the row-form updates pick their tile by the
-    // output's size: the reduction length changes the work per tile, not
+    // output's area: the reduction length changes the work per tile, not
     // how many tiles fill the GPU (a 2048 x 2048 product with K = 4096 needs
     // the tile of 2048^3, not that of 4096^3, which leaves half the compute
-    // units idle).  Their table entries are searched on square problems, for
-    // which both rules agree.  The covariance family keeps the sample count
+    // units idle; an 8192 x 256 output needs the tile of the square of the
+    // same area).  Their table entries are searched on square problems, for
+    // which the rules agree.  The covariance family keeps the sample count
     // in its bucket: its split and stream-K candidates depend on it.
     const bool by_output = kernel == LI_KERNEL_GEMM_F32 || kernel == LI_KERNEL_GEMM_LP ||
                            kernel == LI_KERNEL_GEMM_LP_SPLIT || kernel == LI_KERNEL_SYRK_ROWS;
-    const int b = li_tune_bucket(M, N, by_output ? 0 : K);
+    int b;
+    if (by_output) {
+        // side of the square with the output's area
+        int64_t s = (int64_t)sqrt((double)M * (double)N);
+        while (s * s > M * N) --s;
+        while ((s + 1) * (s + 1) <= M * N) ++s;
+        b = li_tune_bucket(s, s, 0);
+    } else {
+        b = li_tune_bucket(M, N, K);
+    }
     const int t = g_table[kernel][b].load(std::memory_order_relaxed) - 1;
     if (t >= 0) return t;
     return heuristic(kernel, M, N, K);

@@ -186,7 +186,11 @@ def test_tile_choice_by_output_size(li):
             li.li_tune_set(k, b13, 2)
         assert li.li_tune_pick(F, 2048, 2048, 4096) == 1
         assert li.li_tune_pick(F, 2048, 2048, 1024) == 1
-        assert li.li_tune_pick(F, 4096, 2048, 256) == 2
+        assert li.li_tune_pick(F, 4096, 4096, 256) == 2
+        # by area: 8192 x 512 is the square of side 2048
+        assert li.li_tune_pick(F, 8192, 512, 8192) == 1
+        assert li.li_tune_pick(F, 512, 8192, 8192) == 1
+        assert li.li_tune_pick(F, 8192, 2048, 64) == 2
         assert li.li_tune_pick(R, 2048, 2048, 65536) == 1
         assert li.li_tune_pick(S, 2048, 2048, 4096) == 2
         li.li_tune_force(F, 0)
