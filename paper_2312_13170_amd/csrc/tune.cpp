@@ -130,10 +130,14 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
                            kernel == LI_KERNEL_GEMM_LP_SPLIT || kernel == LI_KERNEL_SYRK_ROWS;
     int b;
     if (by_output) {
-        // side of the square with the output's area
+        // side of the square with the output's area (exact where M N fits
+        // in 62 bits, the nearest double's root beyond)
         int64_t s = (int64_t)sqrt((double)M * (double)N);
-        while (s * s > M * N) --s;
-        while ((s + 1) * (s + 1) <= M * N) ++s;
+        if (M < ((int64_t)1 << 31) && N < ((int64_t)1 << 31)) {
+            const int64_t area = M * N;
+            while (s > 0 && s * s > area) --s;
+            while ((s + 1) * (s + 1) <= area) ++s;
+        }
         b = li_tune_bucket(s, s, 0);
     } else {
         b = li_tune_bucket(M, N, K);
