@@ -330,11 +330,16 @@ typedef struct li_tile_config {
                                5-7: modes 1-3 with B transposed into LDS
                                so both operands take 16-byte LDS reads;
                                8: direct HBM-to-LDS loads into a two-stage
-                               ring (mode 2 when K is not a multiple of
-                               the K-tile).  LI_KERNEL_GEMM_LP: the LDS
+                               ring (mode 4 when K is not a multiple of
+                               the K-tile, mode 2 where three stages do
+                               not fit in LDS).  LI_KERNEL_GEMM_LP: the LDS
                                layout instead (1: XOR-swizzled rows, 2:
                                padded rows, 3: layout 1 filled by direct
-                               HBM-to-LDS loads) */
+                               HBM-to-LDS loads, 4: 3 with the next k
+                               step's operands read during the current
+                               step's matrix instructions, 5: 4 with the
+                               direct loads issued between them, 6 / 7: 5
+                               on a four / five stage ring) */
 } li_tile_config;
 
 int32_t li_tune_num_candidates(int32_t kernel);
