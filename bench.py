@@ -16,8 +16,8 @@ Printed: one JSON line with the contract fields, plus
   step          the whole step's rate against the same peak (launch gaps
                 included),
   rows          the other kernels of the path (mean / median / min of 30
-                timed calls after one warm-up; cold-cache times for the
-                HBM-sized ones),
+                timed calls after 100 ms of untimed calls and one warm-up;
+                cold-cache times for the HBM-sized ones),
   cpu_baseline  the FP64 oracle timed on the host cores,
   max_rel_err   every measured result against the FP64 oracle: normwise
                 max|x - ref| / max|ref| (and, for the products, the
@@ -30,7 +30,11 @@ Before the headline's W warm-up steps the same step runs untimed for
 milliseconds to leave idle, longer than a few warm-up steps last, and a
 run that starts timing inside that ramp measures the clock, not the
 kernels.  The other rows follow the headline (after the heavy 8192^3 rows
-the clocks settle lower, so the headline is not measured after them).
+the clocks settle lower, so the headline is not measured after them); each
+row's call first runs untimed for 100 ms for the same reason (the GPU
+idles while the host builds the row's inputs).  Rows whose call updates
+its output in place (beta != 0, mvt's +=) are checked on one clean call
+after the timing, from reset outputs.
 """
 import argparse
 import json
@@ -90,13 +94,28 @@ def parse():
 
 
 class Timer:
-    """HIP events on torch's current stream (the stream every li_* call uses)."""
+    """HIP events on torch's current stream (the stream every li_* call uses).
 
-    def __init__(self, torch):
+    Every measurement first runs the call untimed for settle_ms: between
+    rows the host prepares the next inputs and the GPU idles, and its
+    clocks take tens of milliseconds to come back up, longer than one
+    warm-up call lasts."""
+
+    def __init__(self, torch, settle_ms=100.0):
         self.torch = torch
+        self.settle_ms = settle_ms
+
+    def settle(self, fn):
+        torch = self.torch
+        t0 = time.perf_counter()
+        while (time.perf_counter() - t0) * 1e3 < self.settle_ms:
+            for _ in range(4):
+                fn()
+            torch.cuda.synchronize()
 
     def time(self, fn, reps, warmup):
         torch = self.torch
+        self.settle(fn)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -120,7 +139,7 @@ class Timer:
         every call (a 512 MiB buffer is written first, outside the timed
         events)."""
         torch = self.torch
-        fn()
+        self.settle(fn)
         total = 0.0
         for _ in range(reps):
             flush.fill_(1.0)
@@ -136,6 +155,7 @@ class Timer:
     def time_each(self, fn, reps, warmup):
         """per-call times (ms) for mean / median / min."""
         torch = self.torch
+        self.settle(fn)
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -405,9 +425,12 @@ def mm2_errors(orc, c, tmp_gpu, D_gpu):
 
 # ------------------------------------------------------------------ rows
 
-def stats_profile(kind, torch, li, synth):
+def stats_profile(kind, torch, li, synth, settle_ms=300.0):
     """20 covariance and 20 correlation calls at 4096 x 2048 (after one of
-    each), each preceded by a 512 MiB fill when kind == 'cold'."""
+    each), each preceded by a 512 MiB fill when kind == 'cold'.  Before
+    them the covariance runs untimed for settle_ms (with the same fills), so
+    the calls do not start at idle clocks; a kernel trace of this mode
+    averages the settle calls too."""
     s = synth.workload("stats_4096x2048")
     X = torch.from_numpy(s["data"]).cuda()
     N, M = s["N"], s["M"]
@@ -419,6 +442,13 @@ def stats_profile(kind, torch, li, synth):
     flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda") if kind == "cold" else None
     calls = [lambda: li.li_covariance(M, N, X, Y, mean, out, ws),
              lambda: li.li_correlation(M, N, 0.1, X, Y, mean, std, out, ws)]
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < settle_ms:
+        for _ in range(10):
+            if flush is not None:
+                flush.fill_(1.0)
+            calls[0]()
+        torch.cuda.synchronize()
     for fn in calls:
         fn()
         for _ in range(20):
