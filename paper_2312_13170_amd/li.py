@@ -16,8 +16,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libli.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libli.so is not built (run paper_2312_13170_amd/build.py or "
-                      "__graft_entry__.build()); there is no fallback path")
+    raise ImportError("libli.so is not built (run python -m paper_2312_13170_amd.build); "
+                      "there is no fallback path")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
