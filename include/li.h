@@ -92,9 +92,16 @@ li_status li_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
  * multiply on the matrix cores with FP32 accumulation; LI_BF16X3 splits each
  * operand X into Xh = bf16(X), Xl = bf16(X - Xh) and accumulates
  * Ah*Bh + Ah*Bl + Al*Bh.  The 16-bit copies of A and B live in `workspace`
- * (caller-owned device memory of at least li_gemm_ex_workspace_bytes bytes;
- * may be NULL for LI_FP32).  LI_FP16 turns magnitudes beyond 65504 into
- * infinities, as the format does. */
+ * (caller-owned device memory of at least li_gemm_ex_workspace_bytes bytes).
+ * For LI_FP32 the workspace may be NULL (the li_gemm schedule); with one of
+ * li_gemm_ex_workspace_bytes bytes, shapes whose output tiles would leave
+ * compute units idle (fewer 128 x 128 tiles than compute units, or a last
+ * wave of tiles filling at most 60% of them, with K >= 1024) run a
+ * stream-K schedule: the (tile, K-tile) iterations split evenly over the
+ * compute units, pieces of shared tiles added in a fixed order (results
+ * are deterministic); li_gemm_ex_workspace_bytes is 0 for other shapes.
+ * LI_FP16 turns magnitudes beyond 65504 into infinities, as the format
+ * does. */
 size_t li_gemm_ex_workspace_bytes(int64_t M, int64_t N, int64_t K, li_precision p);
 li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
                      const float *B, float beta, float *C, li_precision p,

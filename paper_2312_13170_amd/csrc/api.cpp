@@ -117,7 +117,10 @@ li_status li_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A, 
 size_t li_gemm_ex_workspace_bytes(int64_t M, int64_t N, int64_t K, li_precision p)
 {
     if (M < 0 || N < 0 || K < 0) return 0;
-    if (p == LI_FP32) return 0;
+    if (p == LI_FP32) {
+        if (li::ensure_device()) return 0;
+        return li::gemm_streamk_bytes(M, N, K);
+    }
     if (p != LI_BF16 && p != LI_FP16 && p != LI_BF16X3) return 0;
     return li::lp_workspace_bytes(M, N, K, (int)p);
 }
@@ -132,6 +135,21 @@ li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *
     if (p != LI_FP32 && p != LI_BF16 && p != LI_FP16 && p != LI_BF16X3)
         return li::fail(LI_ERR_BAD_ENUM, "unknown precision %d", (int)p);
     const bool lp = p != LI_FP32 && ab > 0;
+    // FP32 with a workspace: the stream-K schedule where it pays
+    bool streamk = false;
+    if (p == LI_FP32 && workspace && alpha != 0.f && ab > 0) {
+        if ((s = li::ensure_device())) return s;
+        const size_t need = li::gemm_streamk_bytes(M, N, K);
+        if (need > 0) {
+            if ((s = li::check_workspace(workspace, workspace_bytes, need))) return s;
+            const Span ws{workspace, need};
+            if ((s = li::check_no_overlap("workspace", ws, "A", Span{A, ab})) ||
+                (s = li::check_no_overlap("workspace", ws, "B", Span{B, bb})) ||
+                (s = li::check_no_overlap("workspace", ws, "C", Span{C, cb})))
+                return s;
+            streamk = true;
+        }
+    }
     if (lp) {
         const size_t need = li::lp_workspace_bytes(M, N, K, (int)p);
         if ((s = li::check_workspace(workspace, workspace_bytes, need))) return s;
@@ -143,6 +161,9 @@ li_status li_gemm_ex(int64_t M, int64_t N, int64_t K, float alpha, const float *
     }
     if ((s = li::ensure_device())) return s;
     if (M == 0 || N == 0) return LI_OK;
+    if (streamk)
+        return launched(li::launch_gemm_f32_streamk(M, N, K, alpha, A, B, beta, C, (float *)workspace, stream),
+                        "gemm_f32 stream-K launch");
     if (!lp) {
         const int cfg = li::tune_pick(LI_KERNEL_GEMM_F32, M, N, K);
         return launched(li::launch_gemm_f32(cfg, M, N, K, alpha, A, K, B, N, beta, C, N, stream),

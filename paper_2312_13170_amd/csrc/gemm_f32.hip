@@ -56,6 +56,132 @@ int run_gemm(int64_t M, int64_t N, int64_t K, float alpha, const float *A, int64
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
+// ---------------------------------------------------------- stream-K GEMM
+// The nb output tiles times kt K-tiles form one iteration space split
+// evenly over the G work-groups (the schedule of the symmetric
+// contractions, symm_kernels.h): a range covers whole tiles, stored with
+// alpha and beta at once, and at most two tile pieces, stored raw in the
+// workspace; the fixup adds the pieces of every shared tile in work-group
+// order (deterministic) and applies alpha and beta.  The work per
+// work-group is the same whatever the tile count, so shapes whose tiles
+// leave compute units idle (few tiles and a long K, or a last wave of tiles
+// that fills few of them) keep every unit busy.
+template <class T>
+__global__ __launch_bounds__(T::NT) void gemm_streamk_kernel(const float *__restrict__ A, int64_t lda,
+                                                             const float *__restrict__ B, int64_t ldb,
+                                                             float *__restrict__ C, int64_t ldc,
+                                                             int64_t M, int64_t N, int64_t K, float alpha,
+                                                             float beta, int tiles_n, int nb, int kt,
+                                                             float *__restrict__ part)
+{
+    __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    const int G = gridDim.x, g = blockIdx.x;
+    const int64_t total = (int64_t)nb * kt;
+    const int64_t beg = sk_begin(g, total, G), end = sk_begin(g + 1, total, G);
+    for (int64_t it = beg; it < end;) {
+        const int t = (int)(it / kt);
+        const int64_t tile_end = (int64_t)(t + 1) * kt;
+        const int64_t stop = end < tile_end ? end : tile_end;
+        const int64_t k0 = it - (int64_t)t * kt, k1 = stop - (int64_t)t * kt;
+        const int64_t m0 = (int64_t)(t / tiles_n) * T::BM, n0 = (int64_t)(t % tiles_n) * T::BN;
+        const int64_t kend = k1 * T::BK < K ? k1 * T::BK : K;
+        f32x16 acc[T::TM][T::TN];
+        T::zero(acc);
+        T::mainloop(lds, A, lda, B, ldb, M, N, k0 * T::BK, kend, m0, n0, acc);
+        if (k0 == 0 && k1 == kt) {
+            if (beta != 0.f) {
+                float cv[T::TM][T::TN][16];
+                T::load_c(cv, C, ldc, M, N, m0, n0);
+                T::epilogue_gemm_loaded(acc, cv, C, ldc, M, N, m0, n0, alpha, beta);
+            } else {
+                T::epilogue_gemm(acc, C, ldc, M, N, m0, n0, alpha, 0.f);
+            }
+        } else {
+            store_partial<T>(acc, part + ((int64_t)g * 2 + (it == beg ? 0 : 1)) * T::BM * T::BN,
+                             threadIdx.x);
+        }
+        it = stop;
+    }
+}
+
+// One work-group of the tile's shape per tile; tiles one work-group
+// reduced whole were stored already.
+template <class T>
+__global__ __launch_bounds__(T::NT) void gemm_streamk_fixup_kernel(const float *__restrict__ part,
+                                                                   float *__restrict__ C, int64_t ldc,
+                                                                   int64_t M, int64_t N, float alpha,
+                                                                   float beta, int tiles_n, int nb,
+                                                                   int kt, int G)
+{
+    const int t = blockIdx.x;
+    const int64_t total = (int64_t)nb * kt;
+    const int g0 = sk_owner((int64_t)t * kt, total, G), g1 = sk_owner((int64_t)(t + 1) * kt - 1, total, G);
+    if (g0 == g1) return;
+    f32x16 acc[T::TM][T::TN];
+    T::zero(acc);
+    for (int g = g0; g <= g1; ++g) {
+        // the tile is g's first segment unless g started in an earlier tile
+        const int slot = sk_begin(g, total, G) / kt == t ? 0 : 1;
+        add_partial<T>(acc, part + ((int64_t)g * 2 + slot) * T::BM * T::BN, threadIdx.x);
+    }
+    const int64_t m0 = (int64_t)(t / tiles_n) * T::BM, n0 = (int64_t)(t % tiles_n) * T::BN;
+    if (beta != 0.f) {
+        float cv[T::TM][T::TN][16];
+        T::load_c(cv, C, ldc, M, N, m0, n0);
+        T::epilogue_gemm_loaded(acc, cv, C, ldc, M, N, m0, n0, alpha, beta);
+    } else {
+        T::epilogue_gemm(acc, C, ldc, M, N, m0, n0, alpha, 0.f);
+    }
+}
+
+// The stream-K tile: 128 x 128 x 32 on 16 waves, the three-stage
+// direct-to-LDS ring (which takes ragged ranges); the register path when
+// rows are not 16-byte aligned.
+using SkTileVec = F32Tile<128, 128, 32, 4, 4, false, kLoadVec4, 4>;
+using SkTileScalar = F32Tile<128, 128, 32, 4, 4, false, kLoadScalar, 2>;
+
+struct SkPlan {
+    int tiles_n, nb, kt, G;
+};
+
+// Whether and how the stream-K schedule runs M x N x K: with at least 32
+// K-tiles per output tile, when the tiles number fewer than the compute
+// units or their last wave fills at most 60% of them (and there are fewer
+// than four waves, beyond which that tail matters little).
+bool gemm_streamk_plan(int64_t M, int64_t N, int64_t K, SkPlan &p)
+{
+    constexpr int64_t BM = 128, BN = 128, BK = 32;
+    const int64_t cus = device_cu_count();
+    const int64_t tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN, kt = (K + BK - 1) / BK;
+    const int64_t nb = tm * tn;
+    if (M <= 0 || N <= 0 || kt < 32 || cus <= 0) return false;
+    const int64_t rem = nb % cus;
+    const bool underfilled = nb < cus;
+    const bool short_tail = nb < 4 * cus && rem != 0 && rem * 10 <= cus * 6;
+    if (!underfilled && !short_tail) return false;
+    if (nb > (int64_t)1 << 30 || kt > (int64_t)1 << 30) return false;
+    int64_t G = cus < kStreamMaxGroups ? cus : kStreamMaxGroups;
+    if (G > nb * kt) G = nb * kt;
+    p.tiles_n = (int)tn;
+    p.nb = (int)nb;
+    p.kt = (int)kt;
+    p.G = (int)G;
+    return true;
+}
+
+template <class T>
+int run_gemm_streamk(const SkPlan &p, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                     const float *B, float beta, float *C, float *ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(gemm_streamk_kernel<T>, dim3(p.G), dim3(T::NT), 0, s, A, K, B, N, C, N, M, N, K,
+                       alpha, beta, p.tiles_n, p.nb, p.kt, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(gemm_streamk_fixup_kernel<T>, dim3(p.nb), dim3(T::NT), 0, s, (const float *)ws, C,
+                       N, M, N, alpha, beta, p.tiles_n, p.nb, p.kt, p.G);
+    return (int)hipGetLastError();
+}
+
 }  // namespace
 
 int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
@@ -91,6 +217,24 @@ int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const
     default:
         return (int)hipErrorInvalidValue;
     }
+}
+
+size_t gemm_streamk_bytes(int64_t M, int64_t N, int64_t K)
+{
+    SkPlan p;
+    if (!gemm_streamk_plan(M, N, K, p)) return 0;
+    return (size_t)2 * p.G * 128 * 128 * sizeof(float);
+}
+
+int launch_gemm_f32_streamk(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                            const float *B, float beta, float *C, float *ws, void *stream)
+{
+    SkPlan p;
+    if (!gemm_streamk_plan(M, N, K, p) || !ws) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    const bool v4 = K % 4 == 0 && N % 4 == 0 && aligned16(A) && aligned16(B);
+    return v4 ? run_gemm_streamk<SkTileVec>(p, M, N, K, alpha, A, B, beta, C, ws, s)
+              : run_gemm_streamk<SkTileScalar>(p, M, N, K, alpha, A, B, beta, C, ws, s);
 }
 
 size_t syrk_split_bytes(int64_t n)

@@ -57,6 +57,13 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K);
 int launch_gemm_f32(int cfg, int64_t M, int64_t N, int64_t K, float alpha, const float *A,
                     int64_t lda, const float *B, int64_t ldb, float beta, float *C, int64_t ldc,
                     void *stream);
+// The same product on the stream-K schedule, for shapes whose output tiles
+// leave compute units idle: bytes of partial tiles it needs (0 when the
+// plain schedule is the better one for M x N x K), and the launch, whose
+// workspace holds at least that many bytes (16-byte aligned).
+size_t gemm_streamk_bytes(int64_t M, int64_t N, int64_t K);
+int launch_gemm_f32_streamk(int64_t M, int64_t N, int64_t K, float alpha, const float *A,
+                            const float *B, float beta, float *C, float *ws, void *stream);
 
 // Symmetric contraction S = Y^T Y (Y: N x M row-major), upper block tiles
 // computed and mirrored.  mode 0: S *= scale (covariance); mode 1: diagonal

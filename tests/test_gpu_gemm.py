@@ -221,3 +221,49 @@ def test_mm2_2048_full(li, orc):
     # repeat runs are bitwise identical
     tmp2, D2 = run_mm2(li, c)
     assert np.array_equal(D, D2) and np.array_equal(tmp, tmp2)
+
+
+# li_gemm_ex with LI_FP32 and a workspace: the stream-K schedule for shapes
+# whose 128 x 128 tiles leave compute units idle (few tiles with a long K,
+# or a short last wave of tiles); ragged K-tiles and unaligned rows (the
+# register path) included.  Deterministic: a second call is bitwise equal.
+@pytest.mark.parametrize("shape", [(512, 512, 65536), (3000, 3000, 3000), (8192, 256, 4096),
+                                   (300, 200, 4100), (301, 203, 2051)],
+                         ids=lambda s: "%dx%dx%d" % s)
+def test_fp32_streamk(li, orc, shape):
+    M, N, K = shape
+    say("gemm_ex fp32 stream-K", shape)
+    need = li.li_gemm_ex_workspace_bytes(M, N, K, "fp32")
+    assert need > 0
+    A = synth.uniform_pm1(36, "A", (M, K))
+    B = synth.uniform_pm1(36, "B", (K, N))
+    C0 = synth.uniform_pm1(36, "C", (M, N))
+    ref = orc.gemm(A, B, C0, alpha=1.5, beta=1.2)
+    dA, dB = dev(A), dev(B)
+    ws = empty((need // 4 + 1,), fill=float("nan"))
+    outs = []
+    for _ in range(2):
+        dC = dev(C0)
+        li.li_gemm_ex(M, N, K, 1.5, dA, dB, 1.2, dC, "fp32", ws)
+        outs.append(host(dC))
+    assert normwise(outs[0], ref) < TOL_FP32
+    assert np.array_equal(outs[0], outs[1])
+    # beta = 0 with a NaN-filled C: C is only written
+    dC = empty((M, N), fill=float("nan"))
+    li.li_gemm_ex(M, N, K, 1.0, dA, dB, 0.0, dC, "fp32", ws)
+    assert normwise(host(dC), orc.gemm(A, B, None, alpha=1.0, beta=0.0)) < TOL_FP32
+
+
+def test_fp32_streamk_workspace_rules(li):
+    say("gemm_ex fp32 workspace rules")
+    # shapes the plain schedule fills stay on it (no workspace needed)
+    assert li.li_gemm_ex_workspace_bytes(2048, 2048, 2048, "fp32") == 0
+    assert li.li_gemm_ex_workspace_bytes(512, 512, 512, "fp32") == 0  # K too short to split
+    M, N, K = 512, 512, 65536
+    need = li.li_gemm_ex_workspace_bytes(M, N, K, "fp32")
+    dA, dB, dC = empty((M, K), fill=0.0), empty((K, N), fill=0.0), empty((M, N), fill=0.0)
+    short = empty((need // 4 - 1,))
+    with pytest.raises(li.LiError):
+        li.li_gemm_ex(M, N, K, 1.0, dA, dB, 0.0, dC, "fp32", short)
+    # no workspace: the plain schedule
+    li.li_gemm_ex(M, N, K, 1.0, dA, dB, 0.0, dC, "fp32", None)
