@@ -352,18 +352,25 @@ typedef struct li_tile_config {
 int32_t li_tune_num_candidates(int32_t kernel);
 li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out);
 /* Size bucket of a problem: bucket = the number of bits of max(M, N, K)
- * (0..63); problems in one bucket share a table entry.  The GEMM families
- * (LI_KERNEL_GEMM_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_GEMM_LP_SPLIT) and the
- * row-form updates (LI_KERNEL_SYRK_ROWS) look their entry up by the
- * output's area alone, as li_tune_bucket(s, s, 0) with s = floor(sqrt(M N));
- * the other families with all three sizes. */
+ * (0..63). */
 int32_t li_tune_bucket(int64_t M, int64_t N, int64_t K);
-/* Set / get the candidate used for (kernel, bucket); -1 restores the
+/* The table slot (0..63) a call of family `kernel` on an M x N x K problem
+ * reads; problems with one slot share a table entry.  The GEMM families
+ * (LI_KERNEL_GEMM_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_GEMM_LP_SPLIT) and the
+ * row-form updates (LI_KERNEL_SYRK_ROWS) key by the output's area alone:
+ * li_tune_bucket(s, s, 0) with s = floor(sqrt(M N)).  The covariance
+ * family (called as (M, M, N): features, features, samples) keys by
+ * min(li_tune_bucket(M, 0, 0), 15) + 16 c, where the sample class c is 0
+ * for N < 1.5 M, 1 for N < 3 M, 2 for N < 6 M and 3 beyond (3 for M = 0).
+ * The grouped families use li_tune_bucket(M, N, K).  -1 for an unknown
+ * family or a negative size. */
+int32_t li_tune_key(int32_t kernel, int64_t M, int64_t N, int64_t K);
+/* Set / get the candidate used for (kernel, table slot); -1 restores the
  * built-in default. */
 li_status li_tune_set(int32_t kernel, int32_t bucket, int32_t index);
 int32_t li_tune_get(int32_t kernel, int32_t bucket);
 /* The candidate a call of family `kernel` on an M x N x K problem uses now
- * (the forced one, else the table entry of its bucket, else the built-in
+ * (the forced one, else the table entry of its slot, else the built-in
  * default); -1 for an unknown family or a negative size.  For the
  * covariance family pass (M, M, N): features, features, samples. */
 int32_t li_tune_pick(int32_t kernel, int64_t M, int64_t N, int64_t K);

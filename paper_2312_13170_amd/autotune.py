@@ -1,18 +1,19 @@
 #!/usr/bin/env python3
 """Tile-shape search for the kernel families of libli.so.
 
-For each family and size bucket, every compiled candidate is forced in turn
+For each family and table slot, every compiled candidate is forced in turn
 (li_tune_force) and the ordinary entry point is timed with HIP events on
 the current stream (1 warm-up, then the mean of `reps` calls); the fastest
 candidate is written to the table (li_tune_set) and the table is saved as
 text (li_tune_save), which li.py loads at import.
 
-Representative problems per bucket (bucket = bit length of max(M, N, K);
-the GEMM and row-form families look their entry up by the output's size,
-which for the square problems searched here is the same bucket):
-square GEMMs 256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of
-N = 2 M samples for M = 256 .. 2048, square syrk of order 256 .. 4096 and
-square reduced-precision GEMMs.  For the grouped plans, the shape class per
+Representative problems per table slot (li_tune_key: the GEMM and
+row-form families key by the output's area, which for the square problems
+searched here is the bit length of the side; the covariance family by the
+order of the result and the class of the sample count): square GEMMs
+256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of M = 128 ..
+4096 features with N = M, 2 M, 4 M and 8 M samples, square syrk of order
+256 .. 4096 and square reduced-precision GEMMs.  For the grouped plans, the shape class per
 bucket is searched on plans of 64 rectangular problems of one kind with
 sizes drawn log-uniform inside the bucket (32 to 1024, the batch's range):
 each class is forced while the plan is built and the graph launch is
@@ -54,8 +55,7 @@ def gemm_case(n):
     return (n, n, n), lambda: li.li_gemm(n, n, n, 1.5, A, B, 1.2, C)
 
 
-def syrk_case(m):
-    n = 2 * m
+def syrk_case(m, n):
     X = torch.from_numpy(synth.uniform_pm1(91, "X", (n, m))).cuda()
     Y = torch.empty_like(X)
     mean = torch.empty(m, dtype=torch.float64, device="cuda")
@@ -92,7 +92,7 @@ def warm_up(fn, seconds=0.5):
 
 def search(kernel, cases, reps, log, passes=2):
     for label, (shape, fn) in cases:
-        bucket = li.li_tune_bucket(*shape)
+        slot = li.li_tune_key(kernel, *shape)
         n = li.li_tune_num_candidates(kernel)
         warm_up(fn)
         # every candidate timed in `passes` sweeps, the best sweep kept, so
@@ -106,8 +106,8 @@ def search(kernel, cases, reps, log, passes=2):
                 times[idx] = min(times.get(idx, t), t)
         li.li_tune_force(kernel, -1)
         best = min(times, key=times.get)
-        li.li_tune_set(kernel, bucket, best)
-        rec = {"kernel": kernel, "case": label, "bucket": bucket, "best": best,
+        li.li_tune_set(kernel, slot, best)
+        rec = {"kernel": kernel, "case": label, "slot": slot, "best": best,
                "candidate": li.li_tune_candidate(kernel, best),
                "ms": {str(k): round(v, 4) for k, v in times.items()}}
         log.append(rec)
@@ -191,8 +191,10 @@ def main():
         gsizes = [512, 2048] if a.quick else [256, 512, 1024, 2048, 4096, 8192]
         search(li.LI_KERNEL_GEMM_F32, [("gemm %d" % n, gemm_case(n)) for n in gsizes], reps, log)
     if "syrk" in only:
-        ssizes = [512, 2048] if a.quick else [256, 512, 1024, 2048]
-        search(li.LI_KERNEL_SYRK_F32, [("cov M=%d" % m, syrk_case(m)) for m in ssizes], reps, log)
+        ssizes = [512, 2048] if a.quick else [128, 256, 512, 1024, 2048, 4096]
+        ratios = [1, 2] if a.quick else [1, 2, 4, 8]
+        search(li.LI_KERNEL_SYRK_F32, [("cov M=%d N=%d" % (m, r * m), syrk_case(m, r * m))
+                                       for m in ssizes for r in ratios], reps, log)
     if "rows" in only:
         rsizes = [1024, 2048] if a.quick else [256, 512, 1024, 2048, 4096]
         search(li.LI_KERNEL_SYRK_ROWS, [("syrk %d" % n, rank_case(n)) for n in rsizes], reps, log)

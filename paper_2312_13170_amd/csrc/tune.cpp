@@ -61,11 +61,11 @@ std::atomic<int> g_forced[kFamilies];
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Built-in choice for buckets the table does not hold (very large or very
-// elongated problems): the shapes the search picked at the largest sizes
-// when the output has at least one tile per compute unit (256 on MI355X),
-// else the stream-K schedule for the symmetric contractions (a long
-// reduction over few output tiles) and smaller tiles for the products.
+// Built-in choice for slots the table does not hold (very large or very
+// elongated problems): for the products, the shapes the search picked at
+// the largest sizes when the output has at least one tile per compute unit
+// (256 on MI355X), else smaller tiles; for the symmetric contractions, the
+// stream-K schedule for a long reduction or a large result.
 int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
 {
     const int64_t cus = 256;
@@ -76,10 +76,14 @@ int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
         return 2;
     }
     if (kernel == LI_KERNEL_SYRK_F32) {
-        // M features (the order of the result), K samples
-        const int64_t t128 = ceil_div(M, 128);
-        if (t128 * (t128 + 1) / 2 >= cus) return 22;  // 128 x 128, eight waves
-        return K >= 1024 ? 20 : 2;                     // stream-K, 16 waves
+        // M features (the order of the result), K samples.  The search
+        // picks the 128 x 128 stream-K schedule (or its eight-wave form,
+        // within 2%) for every order from 2048 to 4096: 1.5x faster than
+        // one 128 x 128 tile per work-group at 4096, where the upper
+        // triangle has twice as many tiles as there are compute units.
+        // Short reductions over small results take 64 x 64 tiles.
+        if (M >= 2048 || K >= 1024) return 20;  // 128 x 128 stream-K, 16 waves
+        return 17;                              // 64 x 64, direct loads, 3-stage ring
     }
     if (kernel == LI_KERNEL_SYRK_ROWS) {
         // M is the order of C, K the reduction length
@@ -114,22 +118,22 @@ const TileCfg &tune_cfg(int kernel, int idx)
     return family(kernel, &n)[idx];
 }
 
-int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
+// Table slot of a call.  The GEMM families and the row-form updates key
+// their entry by the output's area: the reduction length changes the work
+// per tile, not how many tiles fill the GPU (a 2048 x 2048 product with
+// K = 4096 needs the tile of 2048^3, not that of 4096^3, which leaves half
+// the compute units idle; an 8192 x 256 output needs the tile of the
+// square of the same area).  Their entries are searched on square
+// problems, for which the two rules agree.  The covariance family keys by
+// two sizes: the order of the result M (bit length, at most 15), which
+// sets how many output tiles there are, and the class of the sample count
+// N against M (0: N < 1.5 M, 1: below 3 M, 2: below 6 M, 3: beyond), which
+// sets how long each tile's reduction is; split and stream-K candidates
+// trade the two off.  The grouped families key by max(M, N, K).
+int tune_key(int kernel, int64_t M, int64_t N, int64_t K)
 {
-    const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
-    if (f >= 0) return f;
-    // The GEMM families and the row-form updates pick their tile by the
-    // output's area: the reduction length changes the work per tile, not
-    // how many tiles fill the GPU (a 2048 x 2048 product with K = 4096 needs
-    // the tile of 2048^3, not that of 4096^3, which leaves half the compute
-    // units idle; an 8192 x 256 output needs the tile of the square of the
-    // same area).  Their table entries are searched on square problems, for
-    // which the rules agree.  The covariance family keeps the sample count
-    // in its bucket: its split and stream-K candidates depend on it.
-    const bool by_output = kernel == LI_KERNEL_GEMM_F32 || kernel == LI_KERNEL_GEMM_LP ||
-                           kernel == LI_KERNEL_GEMM_LP_SPLIT || kernel == LI_KERNEL_SYRK_ROWS;
-    int b;
-    if (by_output) {
+    if (kernel == LI_KERNEL_GEMM_F32 || kernel == LI_KERNEL_GEMM_LP || kernel == LI_KERNEL_GEMM_LP_SPLIT ||
+        kernel == LI_KERNEL_SYRK_ROWS) {
         // side of the square with the output's area (exact where M N fits
         // in 62 bits, the nearest double's root beyond)
         int64_t s = (int64_t)sqrt((double)M * (double)N);
@@ -138,11 +142,24 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
             while (s > 0 && s * s > area) --s;
             while ((s + 1) * (s + 1) <= area) ++s;
         }
-        b = li_tune_bucket(s, s, 0);
-    } else {
-        b = li_tune_bucket(M, N, K);
+        return li_tune_bucket(s, s, 0);
     }
-    const int t = g_table[kernel][b].load(std::memory_order_relaxed) - 1;
+    if (kernel == LI_KERNEL_SYRK_F32) {
+        int order = li_tune_bucket(M, 0, 0);
+        if (order > 15) order = 15;
+        // N (samples) is the K of the contraction; the (M, M, N) call form
+        const double r = M > 0 ? (double)K / (double)M : 1e30;
+        const int cls = r < 1.5 ? 0 : r < 3.0 ? 1 : r < 6.0 ? 2 : 3;
+        return order + 16 * cls;
+    }
+    return li_tune_bucket(M, N, K);
+}
+
+int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
+{
+    const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
+    if (f >= 0) return f;
+    const int t = g_table[kernel][tune_key(kernel, M, N, K)].load(std::memory_order_relaxed) - 1;
     if (t >= 0) return t;
     return heuristic(kernel, M, N, K);
 }
@@ -203,6 +220,13 @@ int32_t li_tune_get(int32_t kernel, int32_t bucket)
     return li::g_table[kernel][bucket].load() - 1;
 }
 
+int32_t li_tune_key(int32_t kernel, int64_t M, int64_t N, int64_t K)
+{
+    int n;
+    if (!li::family(kernel, &n) || M < 0 || N < 0 || K < 0) return -1;
+    return li::tune_key(kernel, M, N, K);
+}
+
 int32_t li_tune_pick(int32_t kernel, int64_t M, int64_t N, int64_t K)
 {
     int n;
@@ -225,7 +249,7 @@ li_status li_tune_save(const char *path)
     if (!path) return li::fail(LI_ERR_NULL_POINTER, "path is NULL");
     FILE *f = fopen(path, "w");
     if (!f) return li::fail(LI_ERR_NOT_FOUND, "cannot write %s", path);
-    fprintf(f, "# li tuning table (gfx950): kernel bucket candidate\n");
+    fprintf(f, "# li tuning table (gfx950): kernel slot candidate\n");
     for (int k = 0; k < li::kFamilies; ++k)
         for (int b = 0; b < li::kBuckets; ++b) {
             const int v = li::g_table[k][b].load() - 1;
@@ -254,7 +278,7 @@ li_status li_tune_load(const char *path)
         if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0) continue;
         int k, b, v, cnt;
         if (sscanf(p, "%d %d %d %n", &k, &b, &v, &cnt) != 3 || (p[cnt] != 0 && p[cnt] != '#')) {
-            st = li::fail(LI_ERR_INVALID_SIZE, "%s:%d: expected 'kernel bucket candidate'", path, line_no);
+            st = li::fail(LI_ERR_INVALID_SIZE, "%s:%d: expected 'kernel slot candidate'", path, line_no);
             break;
         }
         int nc;

@@ -92,6 +92,7 @@ _SIGS = {
     "li_tune_bucket": ([_i64, _i64, _i64], _i32),
     "li_tune_set": ([_i32, _i32, _i32], _i32),
     "li_tune_get": ([_i32, _i32], _i32),
+    "li_tune_key": ([_i32, _i64, _i64, _i64], _i32),
     "li_tune_pick": ([_i32, _i64, _i64, _i64], _i32),
     "li_tune_force": ([_i32, _i32], _i32),
     "li_tune_save": ([ctypes.c_char_p], _i32),
@@ -351,6 +352,10 @@ def li_tune_set(kernel, bucket, index) -> None:
 
 def li_tune_get(kernel, bucket) -> int:
     return _lib.li_tune_get(kernel, bucket)
+
+
+def li_tune_key(kernel, M, N, K) -> int:
+    return _lib.li_tune_key(kernel, M, N, K)
 
 
 def li_tune_pick(kernel, M, N, K) -> int:

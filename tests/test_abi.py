@@ -175,15 +175,34 @@ def test_tuning_table(li):
 def test_tile_choice_by_output_size(li):
     # The GEMM and row-form families choose by the output's size (a long
     # reduction does not take the tile of a larger square problem); the
-    # covariance family keeps the sample count in its bucket.
+    # covariance family by its order and the class of the sample count.
     F, S, R = li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_SYRK_ROWS
     b12, b13 = li.li_tune_bucket(2048, 2048, 0), li.li_tune_bucket(4096, 4096, 4096)
     assert (b12, b13) == (12, 13)
-    old = {(k, b): li.li_tune_get(k, b) for k in (F, S, R) for b in (b12, b13)}
+    for k in (F, R, li.LI_KERNEL_GEMM_LP, li.LI_KERNEL_GEMM_LP_SPLIT):
+        assert li.li_tune_key(k, 2048, 2048, 4096) == 12
+        assert li.li_tune_key(k, 8192, 512, 64) == 12
+        assert li.li_tune_key(k, 8192, 2048, 64) == 13
+    # covariance: order bits + 16 * sample class (N / M: <1.5, <3, <6, more)
+    for n, slot in ((2048, 12), (3071, 12), (3072, 28), (4096, 28), (6143, 28), (6144, 44),
+                    (12287, 44), (12288, 60), (1, 12), (0, 12)):
+        assert li.li_tune_key(S, 2048, 2048, n) == slot, n
+    assert li.li_tune_key(S, 65536, 65536, 65536) == 15
+    assert li.li_tune_key(S, 0, 0, 5) == 48
+    assert li.li_tune_key(li.LI_KERNEL_GROUPED_COV, 300, 300, 5000) == 13
+    assert li.li_tune_key(7, 8, 8, 8) == -1 and li.li_tune_key(S, 8, 8, -1) == -1
+    old = {(k, b): li.li_tune_get(k, b) for k in (F, S, R) for b in (b12, b13, 28, 30, 6)}
     try:
+        # slots without an entry: stream-K for a large result or a long
+        # reduction, 64 x 64 tiles for a short one over a small result
+        for b in (30, 6):
+            li.li_tune_set(S, b, -1)
+        assert li.li_tune_pick(S, 8192, 8192, 16384) == 20
+        assert li.li_tune_key(S, 40, 40, 50) == 6 and li.li_tune_pick(S, 40, 40, 50) == 17
         for k in (F, S, R):
             li.li_tune_set(k, b12, 1)
             li.li_tune_set(k, b13, 2)
+        li.li_tune_set(S, 28, 3)
         assert li.li_tune_pick(F, 2048, 2048, 4096) == 1
         assert li.li_tune_pick(F, 2048, 2048, 1024) == 1
         assert li.li_tune_pick(F, 4096, 4096, 256) == 2
@@ -192,7 +211,9 @@ def test_tile_choice_by_output_size(li):
         assert li.li_tune_pick(F, 512, 8192, 8192) == 1
         assert li.li_tune_pick(F, 8192, 2048, 64) == 2
         assert li.li_tune_pick(R, 2048, 2048, 65536) == 1
-        assert li.li_tune_pick(S, 2048, 2048, 4096) == 2
+        assert li.li_tune_pick(S, 2048, 2048, 4096) == 3
+        assert li.li_tune_pick(S, 2048, 2048, 2048) == 1
+        assert li.li_tune_pick(S, 4096, 4096, 4096) == 2
         li.li_tune_force(F, 0)
         assert li.li_tune_pick(F, 2048, 2048, 4096) == 0
     finally:
