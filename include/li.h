@@ -356,12 +356,15 @@ li_status li_tune_candidate(int32_t kernel, int32_t index, li_tile_config *out);
 int32_t li_tune_bucket(int64_t M, int64_t N, int64_t K);
 /* The table slot (0..63) a call of family `kernel` on an M x N x K problem
  * reads; problems with one slot share a table entry.  The GEMM families
- * (LI_KERNEL_GEMM_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_GEMM_LP_SPLIT) and the
- * row-form updates (LI_KERNEL_SYRK_ROWS) key by the output's area alone:
- * li_tune_bucket(s, s, 0) with s = floor(sqrt(M N)).  The covariance
- * family (called as (M, M, N): features, features, samples) keys by
- * min(li_tune_bucket(M, 0, 0), 15) + 16 c, where the sample class c is 0
- * for N < 1.5 M, 1 for N < 3 M, 2 for N < 6 M and 3 beyond (3 for M = 0).
+ * (LI_KERNEL_GEMM_F32, LI_KERNEL_GEMM_LP, LI_KERNEL_GEMM_LP_SPLIT) key by
+ * the output's area alone: li_tune_bucket(s, s, 0) with
+ * s = floor(sqrt(M N)).  The covariance family (called as (M, M, N):
+ * features, features, samples) and the row-form updates (LI_KERNEL_SYRK_ROWS,
+ * called as (N, N, K): order, order, rank) key by
+ * min(li_tune_bucket(M, 0, 0), 15) + 16 c with the reduction length K
+ * (covariance: the samples) in class c: for covariance 0 if K < 1.5 M,
+ * 1 if K < 3 M, 2 if K < 6 M, else 3; for the row-form updates 0 if
+ * K < 0.75 M, 1 if K < 3 M, 2 if K < 12 M, else 3 (3 when M = 0).
  * The grouped families use li_tune_bucket(M, N, K).  -1 for an unknown
  * family or a negative size. */
 int32_t li_tune_key(int32_t kernel, int64_t M, int64_t N, int64_t K);

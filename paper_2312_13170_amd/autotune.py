@@ -7,13 +7,14 @@ the current stream (1 warm-up, then the mean of `reps` calls); the fastest
 candidate is written to the table (li_tune_set) and the table is saved as
 text (li_tune_save), which li.py loads at import.
 
-Representative problems per table slot (li_tune_key: the GEMM and
-row-form families key by the output's area, which for the square problems
-searched here is the bit length of the side; the covariance family by the
-order of the result and the class of the sample count): square GEMMs
-256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of M = 128 ..
-4096 features with N = M, 2 M, 4 M and 8 M samples, square syrk of order
-256 .. 4096 and square reduced-precision GEMMs.  For the grouped plans, the shape class per
+Representative problems per table slot (li_tune_key:
+the GEMM families key by the output's area, which for the square problems
+searched here is the bit length of the side; the symmetric contractions by
+the order of the result and the class of the reduction length): square
+GEMMs 256 .. 8192, the 2048^4 two-GEMM chain's shape, covariance of
+M = 128 .. 4096 features with N = M, 2 M, 4 M and 8 M samples, syrk of
+order 256 .. 4096 with rank N / 4, N, 4 N and 16 N, and square
+reduced-precision GEMMs.  For the grouped plans, the shape class per
 bucket is searched on plans of 64 rectangular problems of one kind with
 sizes drawn log-uniform inside the bucket (32 to 1024, the batch's range):
 each class is forced while the plan is built and the graph launch is
@@ -72,11 +73,11 @@ def lp_case(n, prec):
     return (n, n, n), lambda: li.li_gemm_ex(n, n, n, 1.0, A, B, 0.0, C, prec, ws)
 
 
-def rank_case(n):
-    A = torch.from_numpy(synth.uniform_pm1(93, "A", (n, n))).cuda()
+def rank_case(n, k):
+    A = torch.from_numpy(synth.uniform_pm1(93, "A", (n, k))).cuda()
     C = torch.from_numpy(synth.uniform_pm1(93, "C", (n, n))).cuda()
-    ws = torch.empty(li.li_syrk_workspace_bytes(n, n) // 4 + 1, device="cuda")
-    return (n, n, n), lambda: li.li_syrk(n, n, 1.5, A, 1.2, C, ws)
+    ws = torch.empty(li.li_syrk_workspace_bytes(n, k) // 4 + 1, device="cuda")
+    return (n, n, k), lambda: li.li_syrk(n, k, 1.5, A, 1.2, C, ws)
 
 
 def warm_up(fn, seconds=0.5):
@@ -197,7 +198,9 @@ def main():
                                        for m in ssizes for r in ratios], reps, log)
     if "rows" in only:
         rsizes = [1024, 2048] if a.quick else [256, 512, 1024, 2048, 4096]
-        search(li.LI_KERNEL_SYRK_ROWS, [("syrk %d" % n, rank_case(n)) for n in rsizes], reps, log)
+        ranks = [(1, 1)] if a.quick else [(1, 4), (1, 1), (4, 1), (16, 1)]
+        search(li.LI_KERNEL_SYRK_ROWS, [("syrk N=%d K=%d" % (n, n * p // q), rank_case(n, n * p // q))
+                                        for n in rsizes for p, q in ranks], reps, log)
     if "lp" in only:
         lsizes = [2048, 8192] if a.quick else [1024, 2048, 4096, 8192]
         search(li.LI_KERNEL_GEMM_LP, [("bf16 %d" % n, lp_case(n, "bf16")) for n in lsizes], reps, log)

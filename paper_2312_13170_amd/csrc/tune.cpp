@@ -86,10 +86,14 @@ int heuristic(int kernel, int64_t M, int64_t N, int64_t K)
         return 17;                              // 64 x 64, direct loads, 3-stage ring
     }
     if (kernel == LI_KERNEL_SYRK_ROWS) {
-        // M is the order of C, K the reduction length
-        const int64_t t128 = ceil_div(M, 128), up = t128 * (t128 + 1) / 2;
-        if (up >= cus) return 2;
-        return K >= 1024 ? 15 : 9;  // stream-K, 16 waves; else 64 x 64 split
+        // M is the order of C, K the reduction length (the rank).  The
+        // search picks stream-K at every order from 2048 to 4096 unless
+        // the rank is short (1.4x faster than one 128 x 128 tile per
+        // work-group at 4096, rank 4096), unsplit 64 x 64 tiles for a
+        // short rank, and 64 x 64 tiles split in four below.
+        if (4 * K < 3 * M) return 10;            // 64 x 64, one work-group per tile
+        if (M >= 2048 || K >= 4096) return 15;   // 128 x 128 stream-K, 16 waves
+        return 9;                                // 64 x 64, split in four
     }
     if (kernel == LI_KERNEL_GROUPED_GEMM || kernel == LI_KERNEL_GROUPED_COV) {
         // the 128 class when the output has at least 256 rows and columns
@@ -124,16 +128,17 @@ const TileCfg &tune_cfg(int kernel, int idx)
 // K = 4096 needs the tile of 2048^3, not that of 4096^3, which leaves half
 // the compute units idle; an 8192 x 256 output needs the tile of the
 // square of the same area).  Their entries are searched on square
-// problems, for which the two rules agree.  The covariance family keys by
-// two sizes: the order of the result M (bit length, at most 15), which
-// sets how many output tiles there are, and the class of the sample count
-// N against M (0: N < 1.5 M, 1: below 3 M, 2: below 6 M, 3: beyond), which
-// sets how long each tile's reduction is; split and stream-K candidates
-// trade the two off.  The grouped families key by max(M, N, K).
+// problems, for which the two rules agree.  The symmetric contractions key
+// by two sizes: the order of the result M (bit length, at most 15), which
+// sets how many output tiles there are, and a class of the reduction
+// length K against M, which sets how long each tile's reduction is; split
+// and stream-K candidates trade the two off.  Covariance (K = samples)
+// classes: K < 1.5 M, < 3 M, < 6 M, beyond; the row-form updates, whose
+// rank is often below the order: K < 0.75 M, < 3 M, < 12 M, beyond.
+// The grouped families key by max(M, N, K).
 int tune_key(int kernel, int64_t M, int64_t N, int64_t K)
 {
-    if (kernel == LI_KERNEL_GEMM_F32 || kernel == LI_KERNEL_GEMM_LP || kernel == LI_KERNEL_GEMM_LP_SPLIT ||
-        kernel == LI_KERNEL_SYRK_ROWS) {
+    if (kernel == LI_KERNEL_GEMM_F32 || kernel == LI_KERNEL_GEMM_LP || kernel == LI_KERNEL_GEMM_LP_SPLIT) {
         // side of the square with the output's area (exact where M N fits
         // in 62 bits, the nearest double's root beyond)
         int64_t s = (int64_t)sqrt((double)M * (double)N);
@@ -144,12 +149,17 @@ int tune_key(int kernel, int64_t M, int64_t N, int64_t K)
         }
         return li_tune_bucket(s, s, 0);
     }
-    if (kernel == LI_KERNEL_SYRK_F32) {
+    if (kernel == LI_KERNEL_SYRK_F32 || kernel == LI_KERNEL_SYRK_ROWS) {
         int order = li_tune_bucket(M, 0, 0);
         if (order > 15) order = 15;
-        // N (samples) is the K of the contraction; the (M, M, N) call form
+        // called as (M, M, K): the order of the result twice, then the
+        // reduction length (the sample count for covariance)
         const double r = M > 0 ? (double)K / (double)M : 1e30;
-        const int cls = r < 1.5 ? 0 : r < 3.0 ? 1 : r < 6.0 ? 2 : 3;
+        int cls;
+        if (kernel == LI_KERNEL_SYRK_F32)
+            cls = r < 1.5 ? 0 : r < 3.0 ? 1 : r < 6.0 ? 2 : 3;
+        else
+            cls = r < 0.75 ? 0 : r < 3.0 ? 1 : r < 12.0 ? 2 : 3;
         return order + 16 * cls;
     }
     return li_tune_bucket(M, N, K);

@@ -179,7 +179,7 @@ def test_tile_choice_by_output_size(li):
     F, S, R = li.LI_KERNEL_GEMM_F32, li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_SYRK_ROWS
     b12, b13 = li.li_tune_bucket(2048, 2048, 0), li.li_tune_bucket(4096, 4096, 4096)
     assert (b12, b13) == (12, 13)
-    for k in (F, R, li.LI_KERNEL_GEMM_LP, li.LI_KERNEL_GEMM_LP_SPLIT):
+    for k in (F, li.LI_KERNEL_GEMM_LP, li.LI_KERNEL_GEMM_LP_SPLIT):
         assert li.li_tune_key(k, 2048, 2048, 4096) == 12
         assert li.li_tune_key(k, 8192, 512, 64) == 12
         assert li.li_tune_key(k, 8192, 2048, 64) == 13
@@ -188,10 +188,14 @@ def test_tile_choice_by_output_size(li):
                     (12287, 44), (12288, 60), (1, 12), (0, 12)):
         assert li.li_tune_key(S, 2048, 2048, n) == slot, n
     assert li.li_tune_key(S, 65536, 65536, 65536) == 15
+    # row-form updates: order bits + 16 * rank class (K / N: <0.75, <3, <12, more)
+    for k, slot in ((511, 12), (1535, 12), (1536, 28), (2048, 28), (6143, 28), (6144, 44),
+                    (24575, 44), (24576, 60), (65536, 60)):
+        assert li.li_tune_key(R, 2048, 2048, k) == slot, k
     assert li.li_tune_key(S, 0, 0, 5) == 48
     assert li.li_tune_key(li.LI_KERNEL_GROUPED_COV, 300, 300, 5000) == 13
     assert li.li_tune_key(7, 8, 8, 8) == -1 and li.li_tune_key(S, 8, 8, -1) == -1
-    old = {(k, b): li.li_tune_get(k, b) for k in (F, S, R) for b in (b12, b13, 28, 30, 6)}
+    old = {(k, b): li.li_tune_get(k, b) for k in (F, S, R) for b in (b12, b13, 28, 30, 6, 14, 46, 62)}
     try:
         # slots without an entry: stream-K for a large result or a long
         # reduction, 64 x 64 tiles for a short one over a small result
@@ -199,6 +203,11 @@ def test_tile_choice_by_output_size(li):
             li.li_tune_set(S, b, -1)
         assert li.li_tune_pick(S, 8192, 8192, 16384) == 20
         assert li.li_tune_key(S, 40, 40, 50) == 6 and li.li_tune_pick(S, 40, 40, 50) == 17
+        for b in (14, 30, 46, 62):  # 8192 at every rank class
+            li.li_tune_set(R, b, -1)
+        assert li.li_tune_pick(R, 8192, 8192, 1024) == 10
+        assert li.li_tune_pick(R, 8192, 8192, 8192) == 15
+        assert li.li_tune_pick(R, 8192, 8192, 131072) == 15
         for k in (F, S, R):
             li.li_tune_set(k, b12, 1)
             li.li_tune_set(k, b13, 2)
@@ -210,7 +219,7 @@ def test_tile_choice_by_output_size(li):
         assert li.li_tune_pick(F, 8192, 512, 8192) == 1
         assert li.li_tune_pick(F, 512, 8192, 8192) == 1
         assert li.li_tune_pick(F, 8192, 2048, 64) == 2
-        assert li.li_tune_pick(R, 2048, 2048, 65536) == 1
+        assert li.li_tune_pick(R, 2048, 2048, 500) == 1
         assert li.li_tune_pick(S, 2048, 2048, 4096) == 3
         assert li.li_tune_pick(S, 2048, 2048, 2048) == 1
         assert li.li_tune_pick(S, 4096, 4096, 4096) == 2
