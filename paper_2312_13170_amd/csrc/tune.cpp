@@ -165,13 +165,62 @@ int tune_key(int kernel, int64_t M, int64_t N, int64_t K)
     return li_tune_bucket(M, N, K);
 }
 
+// Wave quantisation of the FP32 GEMM.  The table is searched on square
+// powers of two, whose tile counts divide evenly among the 256 compute
+// units; other sizes of the same slot can leave most of the last round of
+// tiles empty (3072^2 in 128 x 128 tiles: 576 tiles, three rounds for
+// 2.25 rounds of work).  A round of one-work-group-per-CU tiles costs its
+// tile area times the shape's relative cost per element (its time per
+// output element at 8192^3, where every shape's tiles divide evenly,
+// against the fastest), so the predicted time of a shape is
+// ceil(tiles / 256) * area * cost.  When the table's choice is predicted
+// more than 5% slower than the best of four steady shapes, that one runs
+// instead.  Below 1536^2 output elements the launch and the pipeline fill
+// dominate and the table stands.
+struct QuantCand {
+    int idx;      // candidate of the FP32 GEMM list (tile shape from there)
+    double cost;  // relative time per output element at 8192^3
+    bool choosable;
+};
+const QuantCand kQuantF32[] = {
+    {49, 1.000, true},   // 128 x 256, direct loads, two-stage ring
+    {44, 1.015, true},   // 128 x 128, 16 waves, direct loads
+    {25, 1.030, true},   // 64 x 128, direct loads, three-stage ring
+    {19, 1.089, true},   // 64 x 64, direct loads, three-stage ring
+    {18, 1.013, false},  // other table choices, costed only
+    {15, 1.065, false},
+    {24, 1.072, false},
+    {20, 1.151, false},
+};
+
+double quant_time(const QuantCand &q, int64_t M, int64_t N)
+{
+    const TileCfg &c = kGemmF32[q.idx];
+    const int64_t tiles = ceil_div(M, c.bm) * ceil_div(N, c.bn);
+    return (double)ceil_div(tiles, 256) * (double)(c.bm * c.bn) * q.cost;
+}
+
+int refine_f32(int t, int64_t M, int64_t N)
+{
+    if ((double)M * (double)N < 1536.0 * 1536.0) return t;
+    const QuantCand *cur = nullptr;
+    for (const QuantCand &q : kQuantF32)
+        if (q.idx == t) cur = &q;
+    if (!cur) return t;
+    const QuantCand *best = nullptr;
+    for (const QuantCand &q : kQuantF32)
+        if (q.choosable && (!best || quant_time(q, M, N) < quant_time(*best, M, N))) best = &q;
+    return quant_time(*cur, M, N) > 1.05 * quant_time(*best, M, N) ? best->idx : t;
+}
+
 int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
 {
     const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
     if (f >= 0) return f;
-    const int t = g_table[kernel][tune_key(kernel, M, N, K)].load(std::memory_order_relaxed) - 1;
-    if (t >= 0) return t;
-    return heuristic(kernel, M, N, K);
+    int t = g_table[kernel][tune_key(kernel, M, N, K)].load(std::memory_order_relaxed) - 1;
+    if (t < 0) t = heuristic(kernel, M, N, K);
+    if (kernel == LI_KERNEL_GEMM_F32) t = refine_f32(t, M, N);
+    return t;
 }
 
 }  // namespace li

@@ -240,6 +240,38 @@ def test_tile_choice_by_output_size(li):
             li.li_tune_force(k, n)
 
 
+def test_f32_wave_quantisation(li):
+    # The table's FP32 GEMM choices are searched on square powers of two;
+    # other sizes of a slot take the steady tile shape with the fewest
+    # wasted tile slots in the last round (256 compute units), when the
+    # table's shape is predicted more than 5% slower.
+    F = li.LI_KERNEL_GEMM_F32
+    slots = {11: 20, 12: 44, 13: 49}
+    old = {b: li.li_tune_get(F, b) for b in slots}
+    try:
+        for b, c in slots.items():
+            li.li_tune_set(F, b, c)
+        # the searched squares keep their entries
+        assert li.li_tune_pick(F, 2048, 2048, 2048) == 44
+        assert li.li_tune_pick(F, 4096, 4096, 4096) == 49
+        assert li.li_tune_pick(F, 1024, 1024, 1024) == 20   # below 1536^2: the table stands
+        # 3072^2 in 128 x 128 tiles: 576 tiles, 3 rounds for 2.25; 64 x 64: 2304, 9 rounds
+        assert li.li_tune_pick(F, 3072, 3072, 3072) == 19
+        # 4500^2: 648 tiles of 128 x 256 (3 rounds for 2.53); 64 x 128: 2556 (10 for 9.98)
+        assert li.li_tune_pick(F, 4500, 4500, 4500) == 25
+        # 6144^2: 1152 tiles of 128 x 256 (5 for 4.5); 128 x 128: 2304 (9 exactly)
+        assert li.li_tune_pick(F, 6144, 6144, 2048) == 44
+        assert li.li_tune_pick(F, 1536, 1536, 1536) == 19
+        # within 5% of the best: 8192 x 1024 stays on the slot's 128 x 128
+        assert li.li_tune_pick(F, 8192, 1024, 4096) == 44
+        li.li_tune_force(F, 49)
+        assert li.li_tune_pick(F, 3072, 3072, 3072) == 49
+    finally:
+        li.li_tune_force(F, -1)
+        for b, v in old.items():
+            li.li_tune_set(F, b, v)
+
+
 def test_group_plan_validation(li):
     P = li.make_problem
     G, COV = li.LI_PROBLEM_GEMM, li.LI_PROBLEM_COVARIANCE
