@@ -165,23 +165,22 @@ int tune_key(int kernel, int64_t M, int64_t N, int64_t K)
     return li_tune_bucket(M, N, K);
 }
 
-// Wave quantisation of the FP32 GEMM.  The table is searched on square
-// powers of two, whose tile counts divide evenly among the 256 compute
-// units; other sizes of the same slot can leave most of the last round of
-// tiles empty (3072^2 in 128 x 128 tiles: 576 tiles, three rounds for
-// 2.25 rounds of work).  A round of one-work-group-per-CU tiles costs its
-// tile area times the shape's relative cost per element (its time per
-// output element at 8192^3, where every shape's tiles divide evenly,
-// against the fastest), so the predicted time of a shape is
-// ceil(tiles / 256) * area * cost.  When the table's choice is predicted
-// more than 5% slower than the best of four steady shapes, that one runs
-// instead.  Below 1536^2 output elements the launch and the pipeline fill
-// dominate and the table stands.
+// Wave quantisation.  The GEMM tables are searched on square powers of
+// two, whose tile counts divide evenly among the 256 compute units; other
+// sizes of the same slot can leave most of the last round of tiles empty
+// (3072^2 in 128 x 128 tiles: 576 tiles, three rounds for 2.25 rounds of
+// work).  A round of one-work-group-per-CU tiles costs its tile area times
+// the shape's relative cost per element, so the predicted time of a shape
+// is ceil(tiles / 256) * area * cost.  When the table's choice is
+// predicted more than 5% slower than the best of a family's steady
+// shapes, that one runs instead.  Below a family's minimum output size the
+// launch and the pipeline fill dominate and the table stands.
 struct QuantCand {
-    int idx;      // candidate of the FP32 GEMM list (tile shape from there)
-    double cost;  // relative time per output element at 8192^3
+    int idx;      // candidate of the family's list (tile shape from there)
+    double cost;  // relative time per output element
     bool choosable;
 };
+// FP32: costs measured at 8192^3, where every shape's tiles divide evenly
 const QuantCand kQuantF32[] = {
     {49, 1.000, true},   // 128 x 256, direct loads, two-stage ring
     {44, 1.015, true},   // 128 x 128, 16 waves, direct loads
@@ -192,25 +191,40 @@ const QuantCand kQuantF32[] = {
     {24, 1.072, false},
     {20, 1.151, false},
 };
+// bf16 / fp16: costs measured from 2048 to 3840, where the 128 x 128 shape
+// runs two rounds and the 256 x 256 one a single round
+const QuantCand kQuantLp[] = {
+    {19, 1.00, true},   // 256 x 256, loads between the matrix instructions
+    {9, 1.88, true},    // 128 x 128, direct loads
+    {23, 1.00, false},  // 256 x 256, four / five stage rings
+    {24, 1.00, false},
+};
 
-double quant_time(const QuantCand &q, int64_t M, int64_t N)
+double quant_time(const TileCfg &c, double cost, int64_t M, int64_t N)
 {
-    const TileCfg &c = kGemmF32[q.idx];
     const int64_t tiles = ceil_div(M, c.bm) * ceil_div(N, c.bn);
-    return (double)ceil_div(tiles, 256) * (double)(c.bm * c.bn) * q.cost;
+    return (double)ceil_div(tiles, 256) * (double)(c.bm * c.bn) * cost;
 }
 
-int refine_f32(int t, int64_t M, int64_t N)
+template <int NQ>
+int refine(const QuantCand (&list)[NQ], const TileCfg *fam, double min_side, int t, int64_t M, int64_t N)
 {
-    if ((double)M * (double)N < 1536.0 * 1536.0) return t;
+    if ((double)M * (double)N < min_side * min_side) return t;
     const QuantCand *cur = nullptr;
-    for (const QuantCand &q : kQuantF32)
+    for (const QuantCand &q : list)
         if (q.idx == t) cur = &q;
     if (!cur) return t;
     const QuantCand *best = nullptr;
-    for (const QuantCand &q : kQuantF32)
-        if (q.choosable && (!best || quant_time(q, M, N) < quant_time(*best, M, N))) best = &q;
-    return quant_time(*cur, M, N) > 1.05 * quant_time(*best, M, N) ? best->idx : t;
+    double tbest = 0;
+    for (const QuantCand &q : list) {
+        if (!q.choosable) continue;
+        const double tq = quant_time(fam[q.idx], q.cost, M, N);
+        if (!best || tq < tbest) {
+            best = &q;
+            tbest = tq;
+        }
+    }
+    return quant_time(fam[cur->idx], cur->cost, M, N) > 1.05 * tbest ? best->idx : t;
 }
 
 int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
@@ -219,7 +233,8 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
     if (f >= 0) return f;
     int t = g_table[kernel][tune_key(kernel, M, N, K)].load(std::memory_order_relaxed) - 1;
     if (t < 0) t = heuristic(kernel, M, N, K);
-    if (kernel == LI_KERNEL_GEMM_F32) t = refine_f32(t, M, N);
+    if (kernel == LI_KERNEL_GEMM_F32) t = refine(kQuantF32, kGemmF32, 1536.0, t, M, N);
+    if (kernel == LI_KERNEL_GEMM_LP) t = refine(kQuantLp, kGemmLp, 2048.0, t, M, N);
     return t;
 }
 

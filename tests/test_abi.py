@@ -240,7 +240,7 @@ def test_tile_choice_by_output_size(li):
             li.li_tune_force(k, n)
 
 
-def test_f32_wave_quantisation(li):
+def test_wave_quantisation(li):
     # The table's FP32 GEMM choices are searched on square powers of two;
     # other sizes of a slot take the steady tile shape with the fewest
     # wasted tile slots in the last round (256 compute units), when the
@@ -270,6 +270,21 @@ def test_f32_wave_quantisation(li):
         li.li_tune_force(F, -1)
         for b, v in old.items():
             li.li_tune_set(F, b, v)
+    # bf16 / fp16: 128 x 128 tiles (candidate 9) up to two rounds, then one
+    # round of 256 x 256 tiles (19); the split-bf16 family is left alone
+    L, LS = li.LI_KERNEL_GEMM_LP, li.LI_KERNEL_GEMM_LP_SPLIT
+    old = {(k, b): li.li_tune_get(k, b) for k in (L, LS) for b in (12, 13)}
+    try:
+        for k in (L, LS):
+            li.li_tune_set(k, 12, 9)
+            li.li_tune_set(k, 13, 19)
+        for n, c in ((2048, 9), (2560, 9), (2816, 9), (3072, 19), (3840, 19), (4096, 19), (7000, 19)):
+            assert li.li_tune_pick(L, n, n, n) == c, n
+        assert li.li_tune_pick(L, 8192, 1024, 8192) == 9
+        assert li.li_tune_pick(LS, 3072, 3072, 3072) == 9
+    finally:
+        for (k, b), v in old.items():
+            li.li_tune_set(k, b, v)
 
 
 def test_group_plan_validation(li):

@@ -267,3 +267,24 @@ def test_fp32_streamk_workspace_rules(li):
         li.li_gemm_ex(M, N, K, 1.0, dA, dB, 0.0, dC, "fp32", short)
     # no workspace: the plain schedule
     li.li_gemm_ex(M, N, K, 1.0, dA, dB, 0.0, dC, "fp32", None)
+
+
+# Sizes that are not powers of two: the table's tile shape (searched on
+# powers of two) would leave most of the last round of tiles empty, and the
+# wave-quantisation refinement picks another shape.  Checked on sampled
+# rows (the last row included) against the oracle.
+@pytest.mark.parametrize("shape", [(3000, 3000, 3000), (4500, 4500, 1000), (1536, 1536, 1536)],
+                         ids=lambda s: "%dx%dx%d" % s)
+def test_refined_tile_pick(li, orc, shape):
+    M, N, K = shape
+    say("gemm refined pick", shape)
+    F = li.LI_KERNEL_GEMM_F32
+    pick = li.li_tune_pick(F, M, N, K)
+    assert pick != li.li_tune_get(F, li.li_tune_key(F, M, N, K))
+    A = synth.uniform_pm1(37, "A", (M, K))
+    B = synth.uniform_pm1(37, "B", (K, N))
+    C0 = synth.uniform_pm1(37, "C", (M, N))
+    out = run_gemm(li, A, B, C0, 1.5, 1.2)
+    rows = np.unique(np.concatenate([np.random.default_rng(37).choice(M, 7, replace=False), [M - 1]]))
+    ref = orc.gemm(A, B, C0, alpha=1.5, beta=1.2, rows=rows)
+    assert normwise(out[rows], ref) < TOL_FP32

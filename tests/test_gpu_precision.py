@@ -109,6 +109,22 @@ def test_against_quantised_oracle(li, orc, precision, shape):
         assert normwise(out, exact) < TOL_FP32
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_refined_tile_pick_3072(li, orc, precision):
+    # 3072^3: the slot's 128 x 128 tiles would run three rounds for 2.25;
+    # the wave-quantisation refinement takes one round of 256 x 256 tiles.
+    # Sampled rows (tile edges and the last row) against the quantised oracle.
+    n = 3072
+    L = li.LI_KERNEL_GEMM_LP
+    assert li.li_tune_pick(L, n, n, n) != li.li_tune_get(L, li.li_tune_key(L, n, n, n))
+    say("lp refined pick", precision, n)
+    inp = synth.precision_inputs(n, n, n, seed=54)
+    A, B = inp["A"], inp["B"]
+    out = run_lp(li, A, B, precision)
+    rows = np.array([0, 1, 127, 128, 255, 256, 1500, 2815, 2816, 3071])
+    assert normwise(out[rows], orc.gemm_quantised(A, B, precision, rows=rows)) < 2e-6
+
+
 @pytest.mark.parametrize("shape", [(300, 520, 200), (70, 260, 40)])
 def test_every_tile_shape(li, orc, shape):
     # every compiled candidate in each 16-bit format (fp16 runs the f16
