@@ -227,6 +227,28 @@ int refine(const QuantCand (&list)[NQ], const TileCfg *fam, double min_side, int
     return quant_time(fam[cur->idx], cur->cost, M, N) > 1.05 * tbest ? best->idx : t;
 }
 
+// Split reductions of the covariance contraction launch (upper-triangle
+// tiles) x (chunks) work-groups, each writing a partial tile.  The table's
+// split choices are searched where that count fits in one round of the
+// 256 compute units; at the top of the same slot (orders up to twice as
+// large) it spills into a second or later round, and with short chunks
+// the partial tiles' traffic weighs as much as the products: there the
+// stream-K schedule of the same tile (balanced ranges, no idle round) is
+// faster (1500 features x 3000 samples: 0.123 ms split in seven, 0.095 ms
+// stream-K; 1900 x 5000 and 1800 x 3600 alike).  Chunks of 4096 and more
+// amortise their partial tile.  The row-form updates keep their table
+// entries: their 64 x 64 split in four stays ahead of stream-K at order
+// 900 (480 work-groups), and no spilled case measured favours the switch
+// by more than a few per cent.
+int refine_cov_split(int t, int64_t M, int64_t K)
+{
+    const TileCfg &c = kSyrkF32[t];
+    if (c.split_k <= 1) return t;
+    const int64_t tt = ceil_div(M, c.bm), up = tt * (tt + 1) / 2;
+    if (up * c.split_k <= 256 || K / c.split_k >= 4096) return t;
+    return c.bm == 128 ? 20 : 21;  // stream-K on the same tile
+}
+
 int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
 {
     const int f = g_forced[kernel].load(std::memory_order_relaxed) - 1;
@@ -235,6 +257,7 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
     if (t < 0) t = heuristic(kernel, M, N, K);
     if (kernel == LI_KERNEL_GEMM_F32) t = refine(kQuantF32, kGemmF32, 1536.0, t, M, N);
     if (kernel == LI_KERNEL_GEMM_LP) t = refine(kQuantLp, kGemmLp, 2048.0, t, M, N);
+    if (kernel == LI_KERNEL_SYRK_F32) t = refine_cov_split(t, M, K);
     return t;
 }
 

@@ -287,6 +287,29 @@ def test_wave_quantisation(li):
             li.li_tune_set(k, b, v)
 
 
+def test_split_spill_takes_stream_k(li):
+    # A covariance split reduction whose (upper tiles) x (chunks) work-groups
+    # spill past one round of 256 compute units with short chunks takes the
+    # stream-K schedule of the same tile; long chunks keep the split, and the
+    # row-form updates keep their table entries.
+    S, R = li.LI_KERNEL_SYRK_F32, li.LI_KERNEL_SYRK_ROWS
+    entries = {(S, 27): 10, (S, 59): 10, (R, 26): 9}
+    old = {kb: li.li_tune_get(*kb) for kb in entries}
+    try:
+        for (k, b), c in entries.items():
+            li.li_tune_set(k, b, c)
+        assert li.li_tune_candidate(S, 10)["split_k"] == 7
+        assert li.li_tune_pick(S, 1024, 1024, 2048) == 10    # 36 tiles x 7 = 252
+        assert li.li_tune_pick(S, 1500, 1500, 3000) == 20    # 78 x 7 = 546, chunks of 428
+        assert li.li_tune_key(S, 1900, 1900, 30000) == 59
+        assert li.li_tune_pick(S, 1900, 1900, 30000) == 10   # 120 x 7 = 840, chunks of 4285
+        assert li.li_tune_pick(R, 1000, 1000, 2000) == 9     # row form: the table stands
+        assert li.li_tune_candidate(S, 20)["split_k"] == 0
+    finally:
+        for (k, b), v in old.items():
+            li.li_tune_set(k, b, v)
+
+
 def test_group_plan_validation(li):
     P = li.make_problem
     G, COV = li.LI_PROBLEM_GEMM, li.LI_PROBLEM_COVARIANCE
