@@ -200,6 +200,15 @@ const QuantCand kQuantLp[] = {
     {24, 1.00, false},
 };
 
+// split-bf16 (both parts of each operand staged; the four-stage layouts
+// do not apply): costs measured from 2048 to 3072
+const QuantCand kQuantLpSplit[] = {
+    {16, 1.00, true},   // 256 x 256, K-tile 64, direct loads
+    {9, 1.60, true},    // 128 x 128, direct loads
+    {12, 1.00, false},  // other 256 x 256 table choices, costed only
+    {15, 1.00, false},
+};
+
 double quant_time(const TileCfg &c, double cost, int64_t M, int64_t N)
 {
     const int64_t tiles = ceil_div(M, c.bm) * ceil_div(N, c.bn);
@@ -257,6 +266,7 @@ int tune_pick(int kernel, int64_t M, int64_t N, int64_t K)
     if (t < 0) t = heuristic(kernel, M, N, K);
     if (kernel == LI_KERNEL_GEMM_F32) t = refine(kQuantF32, kGemmF32, 1536.0, t, M, N);
     if (kernel == LI_KERNEL_GEMM_LP) t = refine(kQuantLp, kGemmLp, 2048.0, t, M, N);
+    if (kernel == LI_KERNEL_GEMM_LP_SPLIT) t = refine(kQuantLpSplit, kGemmLp, 2048.0, t, M, N);
     if (kernel == LI_KERNEL_SYRK_F32) t = refine_cov_split(t, M, K);
     return t;
 }

@@ -271,17 +271,19 @@ def test_wave_quantisation(li):
         for b, v in old.items():
             li.li_tune_set(F, b, v)
     # bf16 / fp16: 128 x 128 tiles (candidate 9) up to two rounds, then one
-    # round of 256 x 256 tiles (19); the split-bf16 family is left alone
+    # round of 256 x 256 tiles (19); split-bf16 alike with its own shapes
     L, LS = li.LI_KERNEL_GEMM_LP, li.LI_KERNEL_GEMM_LP_SPLIT
     old = {(k, b): li.li_tune_get(k, b) for k in (L, LS) for b in (12, 13)}
     try:
-        for k in (L, LS):
-            li.li_tune_set(k, 12, 9)
-            li.li_tune_set(k, 13, 19)
+        li.li_tune_set(L, 12, 9)
+        li.li_tune_set(L, 13, 19)
+        li.li_tune_set(LS, 12, 9)
+        li.li_tune_set(LS, 13, 16)
         for n, c in ((2048, 9), (2560, 9), (2816, 9), (3072, 19), (3840, 19), (4096, 19), (7000, 19)):
             assert li.li_tune_pick(L, n, n, n) == c, n
         assert li.li_tune_pick(L, 8192, 1024, 8192) == 9
-        assert li.li_tune_pick(LS, 3072, 3072, 3072) == 9
+        for n, c in ((2048, 9), (2560, 9), (3072, 16), (3584, 16), (5000, 16)):
+            assert li.li_tune_pick(LS, n, n, n) == c, n
     finally:
         for (k, b), v in old.items():
             li.li_tune_set(k, b, v)

@@ -109,13 +109,13 @@ def test_against_quantised_oracle(li, orc, precision, shape):
         assert normwise(out, exact) < TOL_FP32
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "bf16x3"])
 def test_refined_tile_pick_3072(li, orc, precision):
     # 3072^3: the slot's 128 x 128 tiles would run three rounds for 2.25;
     # the wave-quantisation refinement takes one round of 256 x 256 tiles.
     # Sampled rows (tile edges and the last row) against the quantised oracle.
     n = 3072
-    L = li.LI_KERNEL_GEMM_LP
+    L = li.LI_KERNEL_GEMM_LP_SPLIT if precision == "bf16x3" else li.LI_KERNEL_GEMM_LP
     assert li.li_tune_pick(L, n, n, n) != li.li_tune_get(L, li.li_tune_key(L, n, n, n))
     say("lp refined pick", precision, n)
     inp = synth.precision_inputs(n, n, n, seed=54)
