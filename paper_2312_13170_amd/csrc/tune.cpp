@@ -122,8 +122,8 @@ const TileCfg &tune_cfg(int kernel, int idx)
     return family(kernel, &n)[idx];
 }
 
-// Table slot of a call.  The GEMM families and the row-form updates key
-// their entry by the output's area: the reduction length changes the work
+// Table slot of a call.  The GEMM families key their entry by the
+// output's area: the reduction length changes the work
 // per tile, not how many tiles fill the GPU (a 2048 x 2048 product with
 // K = 4096 needs the tile of 2048^3, not that of 4096^3, which leaves half
 // the compute units idle; an 8192 x 256 output needs the tile of the
