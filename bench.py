@@ -555,24 +555,26 @@ def measure_rows(args, torch, li, synth, timer, checks):
 
     if "vendor" in want:
         # context only: the vendor BLAS behind torch.mm (FP32, no TF32) on
-        # the headline GEMM shape, next to li_gemm on the same operands
-        n = 2048
+        # the headline GEMM shape, and on a size between the searched powers
+        # of two (its tile chosen for wave quantisation), next to li_gemm on
+        # the same operands
         torch.backends.cuda.matmul.allow_tf32 = False
-        c = synth.gemm_inputs(n, n, n, seed=2)
-        A, B = torch.from_numpy(c["A"]).cuda(), torch.from_numpy(c["B"]).cuda()
-        C = torch.empty((n, n), device="cuda")
-        # alternating rounds so both see the same clock state; medians
-        tv, tl = [], []
-        for _ in range(6):
-            tv.append(timer.time(lambda: torch.mm(A, B, out=C), 10, 1))
-            tl.append(timer.time(lambda: li.li_gemm(n, n, n, 1.0, A, B, 0.0, C), 10, 1))
-        ms_v, ms_l = sorted(tv)[3], sorted(tl)[3]
-        f = 2.0 * n ** 3
-        rows["vendor_sgemm_2048"] = {"torch_mm_ms": round(ms_v, 4),
-                                     "torch_mm_TFLOP/s": round(f / ms_v / 1e9, 1),
-                                     "li_gemm_ms": round(ms_l, 4),
-                                     "li_gemm_TFLOP/s": round(f / ms_l / 1e9, 1)}
-        del A, B, C
+        for n in (2048, 3072):
+            c = synth.gemm_inputs(n, n, n, seed=2)
+            A, B = torch.from_numpy(c["A"]).cuda(), torch.from_numpy(c["B"]).cuda()
+            C = torch.empty((n, n), device="cuda")
+            # alternating rounds so both see the same clock state; medians
+            tv, tl = [], []
+            for _ in range(6):
+                tv.append(timer.time(lambda: torch.mm(A, B, out=C), 10, 1))
+                tl.append(timer.time(lambda: li.li_gemm(n, n, n, 1.0, A, B, 0.0, C), 10, 1))
+            ms_v, ms_l = sorted(tv)[3], sorted(tl)[3]
+            f = 2.0 * n ** 3
+            rows["vendor_sgemm_%d" % n] = {"torch_mm_ms": round(ms_v, 4),
+                                           "torch_mm_TFLOP/s": round(f / ms_v / 1e9, 1),
+                                           "li_gemm_ms": round(ms_l, 4),
+                                           "li_gemm_TFLOP/s": round(f / ms_l / 1e9, 1)}
+            del A, B, C
     return rows
 
 
