@@ -372,10 +372,17 @@ int32_t li_tune_key(int32_t kernel, int64_t M, int64_t N, int64_t K);
  * built-in default. */
 li_status li_tune_set(int32_t kernel, int32_t bucket, int32_t index);
 int32_t li_tune_get(int32_t kernel, int32_t bucket);
-/* The candidate a call of family `kernel` on an M x N x K problem uses now
- * (the forced one, else the table entry of its slot, else the built-in
- * default); -1 for an unknown family or a negative size.  For the
- * covariance family pass (M, M, N): features, features, samples. */
+/* The candidate a call of family `kernel` on an M x N x K problem uses now:
+ * the forced one, else the table entry of its slot, else the built-in
+ * default.  Unless forced, the choice is then refined: the GEMM families
+ * (from 1536^2 output elements for FP32, 2048^2 for bf16 / fp16 and
+ * split-bf16) move to another steady tile shape when the chosen one is
+ * predicted more than 5% slower from ceil(tiles / 256) rounds of its tile
+ * area times its relative cost per element; the covariance family moves a
+ * split reduction to the stream-K schedule of the same tile when its
+ * work-groups exceed 256 with chunks under 4096 samples.  -1 for an
+ * unknown family or a negative size.  For the covariance family pass
+ * (M, M, N): features, features, samples. */
 int32_t li_tune_pick(int32_t kernel, int64_t M, int64_t N, int64_t K);
 /* Force one candidate for every call of a family (-1 clears): used by the
  * search to time each candidate through the ordinary entry points. */
